@@ -1,0 +1,209 @@
+"""Benchmark of the free-space Poisson solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--no-cpu] [--no-f64]
+
+One step = one forward solve u = h^2 G1 * f on the 512^3 grid in FP32 (the
+five passes: x-forward, y-forward, z-convolution, y-inverse, x-inverse),
+with f already resident in HBM.  G_hat is built once before timing (setup,
+reported separately).  Prints ONE JSON line.
+
+The per-pass durations come from HIP events recorded on the stream the
+passes are enqueued on (torch's current stream), over the timed steps; the
+roofline object uses the dominant pass.  The FP32 result is compared with the
+FP64 GPU path on the same input (which the test suite pins to the CPU oracle
+at <= 1e-12), and the CPU oracle is timed on a bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
+KERNEL_SOURCES = ("paper_2512_08555_amd/csrc/passes.hip", "paper_2512_08555_amd/csrc/dft.hpp",
+                  "paper_2512_08555_amd/csrc/cplx.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_name, model_bytes):
+    """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
+    profile matches the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(kernel_name)
+    if not ent or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return float(ent["bytes_per_launch"])
+
+
+def time_passes(plan, f, u, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.solve(f, out=u)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[s]
+        e[0].record(stream)
+        plan.run_pass(0, f=f)
+        e[1].record(stream)
+        plan.run_pass(1)
+        e[2].record(stream)
+        plan.run_pass(2)
+        e[3].record(stream)
+        plan.run_pass(3)
+        e[4].record(stream)
+        plan.run_pass(4, u=u)
+        e[5].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_pass = np.zeros(5)
+    total = 0.0
+    for s in range(steps):
+        for k in range(5):
+            per_pass[k] += ev[s][k].elapsed_time(ev[s][k + 1])
+        total += ev[s][0].elapsed_time(ev[s][5])
+    return per_pass / steps, total / steps, wall
+
+
+def cpu_baseline(n_sample=256):
+    """The CPU oracle (scipy.fft, FP64, all host threads) on a bounded sample:
+    one n_sample^3 solve of the same source recipe; G_hat precomputed."""
+    import oracle
+    from paper_2512_08555_amd import workloads
+    workers = len(os.sched_getaffinity(0))
+    workers = min(workers, 16)
+    h = 1.0 / n_sample
+    f = workloads.config_blobs_noise(n_sample, 2)
+    M = (2 * n_sample,) * 3
+    G = oracle.green_spectrum_raw(M)
+    t0 = time.perf_counter()
+    oracle.solve(f, h, G_hat_raw=G, workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample ** 3 / dt, "unit": "grid points/s", "cores": workers, "kind": "oracle",
+            "sample": "one %d^3 FP64 solve by oracle.solve (pruned scipy.fft, %d workers), "
+                      "G_hat precomputed; %.2f s" % (n_sample, workers, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.solver import Plan
+
+    n = args.n
+    h = 1.0 / n
+    f64 = workloads.config_blobs_noise(n, 2)
+    f32_host = f64.astype(np.float32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    plan = Plan((n, n, n), h, "f32")
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    f = torch.from_numpy(f32_host).to(dev)
+    u = torch.empty_like(f)
+    per_pass, step_ms, wall = time_passes(plan, f, u, args.steps, args.warmup)
+    value = n ** 3 / (step_ms * 1e-3)
+    dom = int(np.argmax(per_pass))
+    dom_name = plan.kernel(dom)
+    dom_bytes = plan.model_bytes(dom)
+    achieved = dom_bytes / (per_pass[dom] * 1e-3) / 1e9
+    traffic = load_traffic(dom_name, dom_bytes)
+    total_bytes = plan.model_bytes(-1)
+    kernels = [plan.kernel(k) for k in range(5)]
+
+    extra = {}
+    if not args.no_f64:
+        u32 = plan.solve(f).double()
+        del plan
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        p64 = Plan((n, n, n), h, "f64")
+        torch.cuda.synchronize()
+        setup64 = (time.perf_counter() - t0) * 1e3
+        fd = f.double()   # the same (FP32-rounded) input
+        ud = torch.empty_like(fd)
+        pp64, step64, _ = time_passes(p64, fd, ud, max(3, args.steps // 2), 2)
+        ref = ud
+        d = (u32 - ref)
+        extra = {
+            "f64_pts_per_s": n ** 3 / (step64 * 1e-3),
+            "f64_ms_per_step": step64,
+            "f64_setup_ms": setup64,
+            "f32_speedup_over_f64": step64 / step_ms,
+            "f32_rel_linf_vs_f64": float(d.abs().max() / ref.abs().max()),
+            "f32_rel_l2_vs_f64": float(d.norm() / ref.norm()),
+            "f64_pass_ms": dict(zip(PASS_NAMES, [round(float(x), 4) for x in pp64])),
+        }
+        del p64
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(256 if n >= 256 else n)
+
+    out = {
+        "metric": "grid points/s (512^3 unbounded Poisson solve, FP32)",
+        "value": value,
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (16 seeded Gaussian blobs + 1e-3 zero-mean noise)",
+        "config": {"workload": "free-space Poisson solve, %d^3 cell-centred grid, FP32, "
+                               "padded %d^3 FFT convolution with the 7-point LGF" % (n, 2 * n),
+                   "n": n, "padded": 2 * n, "precision": "f32"},
+        "hbm_gbs_model": total_bytes / (step_ms * 1e-3) / 1e9,
+        "model_bytes_per_step": total_bytes,
+        "pass_ms": dict(zip(PASS_NAMES, [round(float(x), 4) for x in per_pass])),
+        "kernels": kernels,
+        "setup_ms": setup_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": dom_name,
+                     "algorithmic_bytes_per_launch": dom_bytes,
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

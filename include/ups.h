@@ -1,0 +1,173 @@
+/*
+ * ups.h -- C ABI of libups, an MI355X (gfx950) solver for the free-space
+ * ("unbounded") Poisson equation on a uniform 3-D grid.
+ *
+ * What it computes.  The problem is Lap u = f with u -> 0 at infinity
+ * (Poncelet et al., eq. poisson_problem and the unbounded boundary
+ * conditions of Sec. 1 and Sec. 2.2).  The Laplacian is the second-order
+ * 7-point cross stencil of eq. cross_discr2, and the solution is the
+ * convolution of f with that stencil's lattice Green's function G1
+ * (L G1 = delta, Sec. 2.2; Sec. 3.3 requires the kernel to be the LGF of the
+ * operator):
+ *
+ *     u[i] = h^2 sum_{j in box} G1[i - j] f[j]        for every grid point i,
+ *
+ * i.e. the exact decaying solution of the discrete problem for a source that
+ * vanishes outside the box.  It is evaluated in spectral space, u_hat =
+ * G_hat f_hat (Sec. 2.2), on a grid zero-padded to M_i >= 2 N_i - 2 points per
+ * axis (default 2 N_i), with the real, even spectrum G_hat of the evenly
+ * periodised G1 computed once by ups_plan_setup.
+ *
+ * Conventions for every call:
+ *   - Every call returns a ups_status; on failure ups_last_error() holds a
+ *     message (thread-local, valid until the next call on that thread).
+ *   - Arguments are validated before anything is enqueued: a failing call
+ *     leaves no partial work on the stream.
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns all device memory and keeps it alive until the enqueued
+ *     work completes.  The library never allocates device memory.
+ *   - Execution is stream ordered (stream = hipStream_t, NULL = the legacy
+ *     default stream); no call synchronises the host except ups_plan_setup,
+ *     ups_batch_setup and ups_autotune.
+ *   - Real arrays are C-contiguous [component][z][y][x] (x fastest), in the
+ *     plan's precision (double for UPS_F64, float for UPS_F32), aligned to
+ *     2 * sizeof(element) bytes.
+ */
+#ifndef UPS_H
+#define UPS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UPS_ABI_VERSION 1
+
+typedef enum {
+  UPS_OK = 0,
+  UPS_ERR_INVALID_ARG = 1, /* null pointer, bad size, misaligned pointer */
+  UPS_ERR_UNSUPPORTED = 2, /* valid problem this build does not handle */
+  UPS_ERR_WORKSPACE = 3,   /* caller buffer smaller than ups_*_sizes asked */
+  UPS_ERR_DEVICE = 4,      /* no usable gfx950 device, or a HIP call failed */
+  UPS_ERR_NONFINITE = 5,   /* reserved: non-finite input detected */
+  UPS_ERR_INTERNAL = 6,    /* library bug */
+  UPS_ERR_STATE = 7        /* call out of order (e.g. solve before setup) */
+} ups_status;
+
+/* Boundary condition per axis side (Sec. 2.2: unbounded, periodic, even =
+ * homogeneous Neumann, odd = homogeneous Dirichlet).  This build solves
+ * UPS_BC_UNB on all six sides; anything else is UPS_ERR_UNSUPPORTED. */
+typedef enum { UPS_BC_UNB = 0, UPS_BC_PER = 1, UPS_BC_EVEN = 2, UPS_BC_ODD = 3 } ups_bc;
+
+/* Green's kernel: the LGF of the operator the caller discretises with
+ * (Sec. 3.3).  UPS_GREEN_LGF2 = LGF of the 7-point stencil (eq. cross_discr2).
+ * The Mehrstellen kernels of eq. mehrstellen_discr4 / _discr6 are reserved
+ * and return UPS_ERR_UNSUPPORTED. */
+typedef enum { UPS_GREEN_LGF2 = 0, UPS_GREEN_LGF4_MEHR = 1, UPS_GREEN_LGF6_MEHR = 2 } ups_green;
+
+/* Arithmetic of the FFT stages.  UPS_F32 uses float data, float twiddles and a
+ * float G_hat, all rounded from values built in double. */
+typedef enum { UPS_F64 = 0, UPS_F32 = 1 } ups_prec;
+
+/* Sample positions (cell centres or nodes).  Informational: the lattice
+ * convolution does not depend on it. */
+typedef enum { UPS_CELL = 0, UPS_NODE = 1 } ups_center;
+
+typedef struct {
+  int n[3];        /* grid points per axis, (x, y, z); each >= 2          */
+  double h[3];     /* grid spacing per axis; must be equal (isotropic)    */
+  int bc[3][2];    /* ups_bc per axis (x, y, z) and side (low, high)      */
+  int green;       /* ups_green                                           */
+  int prec;        /* ups_prec                                            */
+  int center;      /* ups_center                                          */
+  int ncomp;       /* components solved together (1..8), e.g. 3 for a
+                      vector right-hand side; they share G_hat            */
+  int pad[3];      /* padded FFT length per axis; 0 = 2 n. Must be even,
+                      >= 2 n - 2 and a supported length (ups_supported_length) */
+} ups_problem;
+
+typedef struct ups_plan_s* ups_plan_t;
+typedef struct ups_batch_s* ups_batch_t;
+
+/* Version of this ABI (UPS_ABI_VERSION). */
+int ups_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ups_last_error(void);
+
+/* 1 if `len` is a padded length the compiled kernels handle for precision
+ * `prec`, else 0. */
+int ups_supported_length(int len, int prec);
+
+/* Fill *p with defaults: UNB on every side, LGF2, F64, cell-centred,
+ * ncomp = 1, default padding, n = 0, h = 0. */
+void ups_problem_init(ups_problem* p);
+
+/* Validate the problem and build a host-side plan (no device work).
+ * Errors: INVALID_ARG (null, n < 2, h <= 0, ncomp out of range, pad too small
+ * or odd), UNSUPPORTED (non-UNB side, Mehrstellen kernel, anisotropic h,
+ * padded length without a compiled kernel). */
+ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out);
+
+/* Bytes the caller must provide: green = G_hat octant plus twiddle tables,
+ * persistent between solves; work = solve scratch (also used as scratch by
+ * ups_plan_setup).  Either pointer may be NULL. */
+ups_status ups_plan_sizes(ups_plan_t plan, size_t* green_bytes, size_t* work_bytes);
+
+/* Bind the caller's buffers to the plan and build G_hat (Sec. 2.2) into
+ * `green`: G1 on the octant [0, M_i/2] by a separable Bessel quadrature in
+ * double, its DCT-I along the three axes, times h^2 / (Mx My Mz), rounded to
+ * the plan's precision.  Enqueued on `stream`, then the host waits for it.
+ * The buffers must stay alive and unchanged (green) for every later solve.
+ * Errors: INVALID_ARG (null or misaligned pointers), WORKSPACE (sizes smaller
+ * than ups_plan_sizes), DEVICE (no gfx950 device or a HIP error). */
+ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void* work,
+                          size_t work_bytes, void* stream);
+
+/* u = h^2 G1 * f for each component (Sec. 2.2, u_hat = G_hat f_hat): five
+ * kernels on `stream` -- zero-padded real FFT along x, FFT along y, FFT along
+ * z fused with the multiply by G_hat and the inverse along z, inverse along
+ * y, inverse real FFT along x fused with the crop.  f and u are real arrays
+ * [ncomp][nz][ny][nx]; u may equal f (in place).  f is not modified unless
+ * u == f.  Errors: STATE (setup not done), INVALID_ARG (null/misaligned). */
+ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream);
+
+/* Adjoint of ups_solve: grad_f[j] = h^2 sum_i G1[i - j] grad_u[i].  G1 is
+ * even in every index (the 7-point stencil is symmetric), so this is the
+ * same convolution applied to grad_u; same layout and errors as ups_solve. */
+ups_status ups_solve_adjoint(ups_plan_t plan, const void* grad_u, void* grad_f, void* stream);
+
+/* Name of the kernel variant the plan uses for pass 0..4 (x-forward,
+ * y-forward, z-convolution, y-inverse, x-inverse), or NULL. */
+const char* ups_plan_kernel(ups_plan_t plan, int pass);
+
+/* Select the compiled variant `name` for pass 0..4 (names as returned by
+ * ups_plan_kernel; used by tuning).  INVALID_ARG if no such variant exists
+ * for the pass, precision and padded length. */
+ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
+
+/* Enqueue one pass of the solve on the bound work buffer W, for testing and
+ * per-kernel timing: pass 0 reads the real array `in` and writes W; passes
+ * 1-3 update W in place (in/out ignored); pass 4 reads W and writes the real
+ * array `out`.  W holds complex values [c][z][y][kx] with kx fastest, row
+ * pitch `pitch`, plane stride `plane` and component stride `comp_stride`
+ * (complex elements); G_hat (real, plan precision) sits at byte
+ * `ghat_offset` of the green buffer as [iy][iz][kx], iy stride `ghat_plane`
+ * and iz stride `pitch`. */
+ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, void* stream);
+ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long long* comp_stride,
+                           size_t* ghat_offset, long long* ghat_plane);
+
+/* Algorithmic HBM bytes of pass 0..4 (each element read or written once),
+ * and of the whole solve for pass = -1.  Returns 0 on a bad argument. */
+double ups_plan_model_bytes(ups_plan_t plan, int pass);
+
+/* Release the host-side plan.  Device buffers stay with the caller. */
+ups_status ups_plan_destroy(ups_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UPS_H */

@@ -1,4 +1,4 @@
-"""Lattice Green's function (LGF) of the 7-point Laplacian -- ORACLE, test
+r"""Lattice Green's function (LGF) of the 7-point Laplacian -- ORACLE, test
 infrastructure only (see ``oracle/__init__.py``).
 
 Definition followed (Sec. 2.2, the LGF paragraph): G1 is the solution of

@@ -1,0 +1,356 @@
+// C ABI of libups: problem validation, plans, buffer layout, and the solve
+// entry points.  See include/ups.h for the contract of every call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/ups.h"
+#include "green.hpp"
+#include "passes.hpp"
+#include "plan.hpp"
+
+using namespace ups;
+
+namespace {
+thread_local std::string g_err;
+
+ups_status fail(ups_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+ups_status ok() {
+  g_err.clear();
+  return UPS_OK;
+}
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+namespace ups {
+
+ups_status set_error(ups_status s, const char* msg) { return fail(s, "%s", msg); }
+
+const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name) {
+  const PassVariant* best = nullptr;
+  for (const PassVariant& v : pass_variants()) {
+    if (v.kind != kind || v.is_f64 != (f64 ? 1 : 0) || v.length != length) continue;
+    if (name && std::strcmp(name, v.name) != 0) continue;
+    if (!best) best = &v;
+  }
+  return best;
+}
+
+bool length_supported(int len, bool f64) {
+  return find_variant(PASS_XFWD, f64, len, nullptr) && find_variant(PASS_YFWD, f64, len, nullptr) &&
+         find_variant(PASS_ZCONV, f64, len, nullptr);
+}
+
+ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
+  if (!p) return fail(UPS_ERR_INVALID_ARG, "problem is NULL");
+  for (int i = 0; i < 3; ++i) {
+    if (p->n[i] < 2) return fail(UPS_ERR_INVALID_ARG, "n[%d] = %d: need at least 2 points", i, p->n[i]);
+    if (p->n[i] > 4096) return fail(UPS_ERR_UNSUPPORTED, "n[%d] = %d exceeds 4096", i, p->n[i]);
+    if (!(p->h[i] > 0.0) || !std::isfinite(p->h[i]))
+      return fail(UPS_ERR_INVALID_ARG, "h[%d] must be positive and finite", i);
+    for (int s = 0; s < 2; ++s) {
+      if (p->bc[i][s] < UPS_BC_UNB || p->bc[i][s] > UPS_BC_ODD)
+        return fail(UPS_ERR_INVALID_ARG, "bc[%d][%d] = %d is not a ups_bc", i, s, p->bc[i][s]);
+      if (p->bc[i][s] != UPS_BC_UNB)
+        return fail(UPS_ERR_UNSUPPORTED, "bc[%d][%d]: only unbounded sides are solved", i, s);
+    }
+  }
+  if (std::fabs(p->h[0] - p->h[1]) > 1e-12 * p->h[0] || std::fabs(p->h[0] - p->h[2]) > 1e-12 * p->h[0])
+    return fail(UPS_ERR_UNSUPPORTED, "anisotropic spacing is not supported (h must be equal)");
+  if (p->green < UPS_GREEN_LGF2 || p->green > UPS_GREEN_LGF6_MEHR)
+    return fail(UPS_ERR_INVALID_ARG, "green = %d is not a ups_green", p->green);
+  if (p->green != UPS_GREEN_LGF2)
+    return fail(UPS_ERR_UNSUPPORTED, "only the 7-point LGF kernel (UPS_GREEN_LGF2) is built");
+  if (p->prec != UPS_F64 && p->prec != UPS_F32) return fail(UPS_ERR_INVALID_ARG, "prec = %d", p->prec);
+  if (p->center != UPS_CELL && p->center != UPS_NODE)
+    return fail(UPS_ERR_INVALID_ARG, "center = %d", p->center);
+  if (p->ncomp < 1 || p->ncomp > 8) return fail(UPS_ERR_INVALID_ARG, "ncomp = %d not in 1..8", p->ncomp);
+  const bool f64 = p->prec == UPS_F64;
+  int M[3];
+  for (int i = 0; i < 3; ++i) {
+    M[i] = p->pad[i] ? p->pad[i] : 2 * p->n[i];
+    if (M[i] % 2 || M[i] < 2 * p->n[i] - 2)
+      return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: must be even and >= 2 n - 2 = %d", i, M[i],
+                  2 * p->n[i] - 2);
+  }
+  for (int i = 0; i < 3; ++i) {
+    if (!length_supported(M[i], f64))
+      return fail(UPS_ERR_UNSUPPORTED, "padded length %d (axis %d) has no compiled %s kernel", M[i], i,
+                  f64 ? "double" : "float");
+  }
+  g->f64 = f64;
+  g->elem = f64 ? 8 : 4;
+  g->nx = p->n[0];
+  g->ny = p->n[1];
+  g->nz = p->n[2];
+  g->mx = M[0];
+  g->my = M[1];
+  g->mz = M[2];
+  g->kx = g->mx / 2 + 1;
+  g->oy = g->my / 2 + 1;
+  g->oz = g->mz / 2 + 1;
+  g->px = int(align_up(size_t(g->kx), 16));
+  g->ncomp = p->ncomp;
+  g->h = p->h[0];
+  return UPS_OK;
+}
+
+void plan_layout(PlanGeom& g) {
+  const size_t ce = 2 * g.elem;  // complex element
+  g.plane = (long long)g.my * g.px;
+  g.comp_w = (long long)g.nz * g.plane;
+  g.solve_work = align_up(ce * (size_t)g.comp_w * g.ncomp, 256);
+  const GreenScratch gs = green_scratch_layout(g.oz, g.oy, g.kx);
+  const int mmax = std::max(g.mx, std::max(g.my, g.mz));
+  const size_t setup = std::max(gs.bytes, align_up(sizeof(double) * 2 * (size_t)mmax, 256));
+  g.work_bytes = std::max(g.solve_work, setup);
+  size_t off = 0;
+  g.off_ghat = off;
+  off = align_up(off + g.elem * (size_t)g.oy * g.oz * g.px, 256);
+  g.off_twx = off;
+  off = align_up(off + ce * g.mx, 256);
+  g.off_twy = off;
+  off = align_up(off + ce * g.my, 256);
+  g.off_twz = off;
+  off = align_up(off + ce * g.mz, 256);
+  g.green_bytes = off;
+}
+
+double model_bytes(const PlanGeom& g, int pass) {
+  const double s = double(g.elem), c = 2.0 * s, nc = g.ncomp;
+  const double nxyz = double(g.nx) * g.ny * g.nz;
+  const double xw = double(g.kx) * g.ny * g.nz;        // x-transformed, rows y < ny
+  const double yw = double(g.kx) * g.my * g.nz;        // y-expanded
+  const double gh = double(g.kx) * g.oy * g.oz * s;    // G_hat octant
+  switch (pass) {
+    case 0: return nc * (nxyz * s + xw * c);
+    case 1: return nc * (xw * c + yw * c);
+    case 2: return nc * (2.0 * yw * c) + gh;
+    case 3: return nc * (yw * c + xw * c);
+    case 4: return nc * (xw * c + nxyz * s);
+    case -1: {
+      double t = 0;
+      for (int i = 0; i < 5; ++i) t += model_bytes(g, i);
+      return t;
+    }
+    default: return 0.0;
+  }
+}
+
+ups_status check_device(int* dev_out) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(UPS_ERR_DEVICE, "no HIP device available");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(UPS_ERR_DEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(UPS_ERR_DEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(UPS_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only", dev,
+                prop.gcnArchName);
+  *dev_out = dev;
+  return UPS_OK;
+}
+
+PassArgs make_args(const PlanGeom& g, const void* green) {
+  PassArgs a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.mx = g.mx;
+  a.my = g.my;
+  a.mz = g.mz;
+  a.kx = g.kx;
+  a.px = g.px;
+  a.plane = g.plane;
+  a.comp_w = g.comp_w;
+  a.comp_f = (long long)g.nx * g.ny * g.nz;
+  a.g_plane = (long long)g.oz * g.px;
+  a.ncomp = g.ncomp;
+  const char* gb = static_cast<const char*>(green);
+  a.ghat = gb + g.off_ghat;
+  a.tw_x = gb + g.off_twx;
+  a.tw_y = gb + g.off_twy;
+  a.tw_z = gb + g.off_twz;
+  return a;
+}
+
+ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a,
+                         const void* f, void* u, void* work, hipStream_t st) {
+  var[0]->launch(a, f, work, st);
+  var[1]->launch(a, work, work, st);
+  var[2]->launch(a, work, work, st);
+  var[3]->launch(a, work, work, st);
+  var[4]->launch(a, work, u, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return UPS_OK;
+}
+
+}  // namespace ups
+
+// ============================================================================
+extern "C" {
+
+int ups_abi_version(void) { return UPS_ABI_VERSION; }
+
+const char* ups_last_error(void) { return g_err.c_str(); }
+
+int ups_supported_length(int len, int prec) {
+  if (len < 2 || len % 2) return 0;
+  return length_supported(len, prec == UPS_F64) ? 1 : 0;
+}
+
+void ups_problem_init(ups_problem* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->green = UPS_GREEN_LGF2;
+  p->prec = UPS_F64;
+  p->center = UPS_CELL;
+  p->ncomp = 1;
+}
+
+ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
+  if (!out) return fail(UPS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  PlanGeom g{};
+  ups_status s = validate_problem(prob, &g);
+  if (s != UPS_OK) return s;
+  plan_layout(g);
+  const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
+  const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
+  ups_plan_s* p = new ups_plan_s();
+  p->prob = *prob;
+  p->g = g;
+  for (int i = 0; i < 5; ++i) {
+    p->var[i] = find_variant(kinds[i], g.f64, len[i], nullptr);
+    if (!p->var[i]) {
+      delete p;
+      return fail(UPS_ERR_UNSUPPORTED, "no kernel for pass %d at length %d", i, len[i]);
+    }
+  }
+  *out = p;
+  return ok();
+}
+
+ups_status ups_plan_sizes(ups_plan_t plan, size_t* green_bytes, size_t* work_bytes) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (green_bytes) *green_bytes = plan->g.green_bytes;
+  if (work_bytes) *work_bytes = plan->g.work_bytes;
+  return ok();
+}
+
+ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void* work, size_t work_bytes,
+                          void* stream) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (!green || !work) return fail(UPS_ERR_INVALID_ARG, "green and work must be device pointers");
+  if ((reinterpret_cast<uintptr_t>(green) | reinterpret_cast<uintptr_t>(work)) & 255)
+    return fail(UPS_ERR_INVALID_ARG, "green and work must be 256-byte aligned");
+  const PlanGeom& g = plan->g;
+  if (green_bytes < g.green_bytes)
+    return fail(UPS_ERR_WORKSPACE, "green buffer has %zu bytes, plan needs %zu", green_bytes, g.green_bytes);
+  if (work_bytes < g.work_bytes)
+    return fail(UPS_ERR_WORKSPACE, "work buffer has %zu bytes, plan needs %zu", work_bytes, g.work_bytes);
+  int dev = 0;
+  ups_status s = check_device(&dev);
+  if (s != UPS_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* gb = static_cast<char*>(green);
+  hipError_t e = build_twiddles(g.f64, g.mx, gb + g.off_twx, work, st);
+  if (e == hipSuccess) e = build_twiddles(g.f64, g.my, gb + g.off_twy, work, st);
+  if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, gb + g.off_twz, work, st);
+  if (e == hipSuccess)
+    e = build_green(g.f64, g.oz, g.oy, g.kx, g.px, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "setup failed: %s", hipGetErrorString(e));
+  plan->green = green;
+  plan->work = work;
+  plan->device = dev;
+  plan->args = make_args(g, green);
+  plan->ready = true;
+  return ok();
+}
+
+static ups_status check_io(ups_plan_t plan, const void* in, const void* out) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan->ready) return fail(UPS_ERR_STATE, "ups_plan_setup has not completed on this plan");
+  if (!in || !out) return fail(UPS_ERR_INVALID_ARG, "input and output must be device pointers");
+  const uintptr_t al = 2 * plan->g.elem - 1;
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & al)
+    return fail(UPS_ERR_INVALID_ARG, "arrays must be aligned to %zu bytes", size_t(al + 1));
+  return UPS_OK;
+}
+
+ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
+  ups_status s = check_io(plan, f, u);
+  if (s != UPS_OK) return s;
+  s = enqueue_solve(plan->g, plan->var, plan->args, f, u, plan->work, static_cast<hipStream_t>(stream));
+  return s == UPS_OK ? ok() : s;
+}
+
+ups_status ups_solve_adjoint(ups_plan_t plan, const void* grad_u, void* grad_f, void* stream) {
+  // K^T = K: G1[i - j] = G1[j - i] for the symmetric 7-point stencil.
+  return ups_solve(plan, grad_u, grad_f, stream);
+}
+
+ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, void* stream) {
+  if (pass < 0 || pass > 4) return fail(UPS_ERR_INVALID_ARG, "pass %d not in 0..4", pass);
+  const void* i = pass == 0 ? in : plan ? plan->work : nullptr;
+  void* o = pass == 4 ? out : plan ? plan->work : nullptr;
+  ups_status s = check_io(plan, i, o);
+  if (s != UPS_OK) return s;
+  plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long long* comp_stride,
+                           size_t* ghat_offset, long long* ghat_plane) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (pitch) *pitch = plan->g.px;
+  if (plane) *plane = plan->g.plane;
+  if (comp_stride) *comp_stride = plan->g.comp_w;
+  if (ghat_offset) *ghat_offset = plan->g.off_ghat;
+  if (ghat_plane) *ghat_plane = (long long)plan->g.oz * plan->g.px;
+  return ok();
+}
+
+const char* ups_plan_kernel(ups_plan_t plan, int pass) {
+  if (!plan || pass < 0 || pass > 4) return nullptr;
+  return plan->var[pass]->name;
+}
+
+ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name) {
+  if (!plan || pass < 0 || pass > 4 || !name) return fail(UPS_ERR_INVALID_ARG, "bad plan, pass or name");
+  const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
+  const int len[5] = {plan->g.mx, plan->g.my, plan->g.mz, plan->g.my, plan->g.mx};
+  const PassVariant* v = find_variant(kinds[pass], plan->g.f64, len[pass], name);
+  if (!v) return fail(UPS_ERR_INVALID_ARG, "no variant '%s' for pass %d at length %d", name, pass, len[pass]);
+  plan->var[pass] = v;
+  return ok();
+}
+
+double ups_plan_model_bytes(ups_plan_t plan, int pass) {
+  if (!plan || pass < -1 || pass > 4) return 0.0;
+  return model_bytes(plan->g, pass);
+}
+
+ups_status ups_plan_destroy(ups_plan_t plan) {
+  delete plan;
+  return ok();
+}
+
+}  // extern "C"

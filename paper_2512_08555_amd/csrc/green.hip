@@ -1,0 +1,396 @@
+// Green's spectrum builder (setup, double precision on the device).
+//
+// G1, the lattice Green's function of the 7-point Laplacian (L G1 = delta,
+// paper Sec. 2.2, stencil of eq. cross_discr2), has the Fourier integral
+//   G1[n] = -(2pi)^-3 \int e^{i k.n} / sigma(k) dk,  sigma = sum_i (2 - 2 cos k_i),
+// and with 1/sigma = \int_0^inf e^{-sigma t} dt and the Bessel generating
+// integral it becomes separable:
+//   G1[n] = - \int_0^inf prod_i e^{-2t} I_{n_i}(2t) dt.
+// The integral on [0, T] uses composite 16-point Gauss-Legendre panels of
+// width 1 in s = ln t on [-40, ln T]; on [T, inf) each factor is replaced by
+// its large-argument expansion e^{-x} I_n(x) ~ (2 pi x)^-1/2 sum_k c_k(n) x^-k,
+// c_k(n) = (-1)^k prod_{m<=k} (4n^2 - (2m-1)^2) / (k! 8^k), whose product is
+// integrated term by term.  Both parts are sums of products of per-axis
+// factors, so the whole octant is one contraction
+//   S[nz][ny][nx] = sum_col Az[nz][col] Ay[ny][col] Ax[nx][col],  G1 = -S,
+// evaluated as a batched GEMM.  e^{-x} I_n(x) at the quadrature nodes comes
+// from Miller's backward recurrence normalised by e^{-x}(I_0 + 2 sum I_k) = 1.
+//
+// G_hat on the octant is the DCT-I of G1 along each axis (the DFT of the
+// evenly periodised kernel), applied as three GEMMs with the cosine matrix,
+// each rotating the axes (z,y,x) -> (x,z,y) so the next axis comes last.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "green.hpp"
+#include "cplx.hpp"
+
+namespace ups {
+
+// ---------------------------------------------------------------------------
+// host: Gauss-Legendre rule (Newton on P_n, Abramowitz & Stegun 25.4.29)
+// ---------------------------------------------------------------------------
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+      }
+      dp = n * (z * p0 - p1) / (z * z - 1.0);
+      double dz = p0 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    x[i] = -z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void lgf_quadrature(int n_max, std::vector<double>& t, std::vector<double>& w, double* T_out) {
+  const double T = std::max(400.0, 40.0 * double(n_max) * double(n_max));
+  const double s_lo = -40.0, s_hi = std::log(T);
+  const int npan = int(std::ceil((s_hi - s_lo) / 1.0));
+  std::vector<double> gx, gw;
+  gauss_legendre(16, gx, gw);
+  t.clear();
+  w.clear();
+  for (int p = 0; p < npan; ++p) {
+    const double a = s_lo + (s_hi - s_lo) * p / npan;
+    const double b = s_lo + (s_hi - s_lo) * (p + 1) / npan;
+    const double half = 0.5 * (b - a), mid = 0.5 * (b + a);
+    for (int i = 0; i < 16; ++i) {
+      const double s = mid + half * gx[i];
+      const double ts = std::exp(s);
+      t.push_back(ts);
+      w.push_back(half * gw[i] * ts);  // dt = t ds
+    }
+  }
+  *T_out = T;
+}
+
+// ---------------------------------------------------------------------------
+// device: e^{-x} I_k(x) for k < kmax at x = 2 t_j, one thread per node
+// ---------------------------------------------------------------------------
+__global__ void k_bessel_ive(const double* __restrict__ t, int J, int kmax, double* __restrict__ B) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const double x = 2.0 * t[j];
+  const int top = kmax + 32 + int(10.0 * sqrt(x));
+  const double big = 1e200, small = 1e-200;
+  double ip = 0.0;      // I_{k+1}
+  double ic = 1e-280;   // I_k, k = top
+  double sum = 0.0, comp = 0.0;  // compensated sum over k >= 1 of I_k
+  for (int k = top; k >= 1; --k) {
+    // I_{k-1} = I_{k+1} + (2k/x) I_k
+    const double in = ip + (2.0 * k / x) * ic;
+    {
+      const double yk = ic - comp;
+      const double tk = sum + yk;
+      comp = (tk - sum) - yk;
+      sum = tk;
+    }
+    if (k < kmax) B[(size_t)k * J + j] = ic;
+    ip = ic;
+    ic = in;
+    if (fabs(ic) > big) {
+      ip *= small;
+      ic *= small;
+      sum *= small;
+      comp *= small;
+      const int hi = top < kmax - 1 ? top : kmax - 1;
+      for (int m = k; m <= hi; ++m) B[(size_t)m * J + j] *= small;
+    }
+  }
+  // ic = I_0
+  const double norm = ic + 2.0 * sum;
+  B[j] = ic / norm;
+  const double inv = 1.0 / norm;
+  for (int m = 1; m < kmax; ++m) B[(size_t)m * J + j] *= inv;
+}
+
+// Per-axis factor table A[n][col], col < J: quadrature (weight w folded in
+// when `weighted`), col = J + p: tail pair p = (a, b) with a + b <= K.
+//   role 0 (z): c_a(n)           role 1 (y): c_b(n)
+//   role 2 (x): sum_{c <= K-a-b} c_c(n) g[a+b+c],
+//   g[m] = (4 pi)^-3/2 2^-m T^{-1/2-m} / (m + 1/2).
+constexpr int kTailK = 6;
+constexpr int kTailPairs = (kTailK + 1) * (kTailK + 2) / 2;
+
+__device__ double hankel_c(int k, double n) {
+  double mu = 4.0 * n * n, prod = 1.0, fact = 1.0, p8 = 1.0;
+  for (int m = 1; m <= k; ++m) {
+    prod *= (mu - double((2 * m - 1) * (2 * m - 1)));
+    fact *= m;
+    p8 *= 8.0;
+  }
+  return ((k & 1) ? -1.0 : 1.0) * prod / (fact * p8);
+}
+
+__global__ void k_axis_table(const double* __restrict__ B, const double* __restrict__ w, int J, int kext,
+                             int role, double T, double* __restrict__ A) {
+  const int cols = J + kTailPairs;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)kext * cols) return;
+  const int n = int(idx / cols), col = int(idx % cols);
+  double v;
+  if (col < J) {
+    v = B[(size_t)n * J + col];
+    if (role == 0) v *= w[col];
+  } else {
+    int p = col - J, a = 0;
+    while (p > kTailK - a) { p -= kTailK - a + 1; ++a; }
+    const int b = p;
+    if (role == 0) {
+      v = hankel_c(a, n);
+    } else if (role == 1) {
+      v = hankel_c(b, n);
+    } else {
+      v = 0.0;
+      const double c0 = pow(4.0 * kPi, -1.5);
+      for (int c = 0; c <= kTailK - a - b; ++c) {
+        const int m = a + b + c;
+        const double g = c0 * pow(2.0, -m) * pow(T, -0.5 - m) / (m + 0.5);
+        v += hankel_c(c, n) * g;
+      }
+    }
+  }
+  A[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// device: batched double GEMM-NT with an optional per-batch column scale
+//   out[b][i][j] = alpha * sum_l (S ? S[b*ldS + l] : 1) * X[i][l] * Y[j][l]
+// 64x64 output tile per workgroup, 256 threads with 4x4 outputs each.
+// ---------------------------------------------------------------------------
+constexpr int GT = 64, GK = 16;
+__global__ void __launch_bounds__(256)
+k_gemm_nt(const double* __restrict__ X, int ni, const double* __restrict__ Y, int nj, int nl,
+          const double* __restrict__ S, long long ldS, double alpha, double* __restrict__ out,
+          long long out_bstride) {
+  __shared__ double xs[GK][GT + 1];
+  __shared__ double ys[GK][GT + 1];
+  const int b = blockIdx.z;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  double acc[4][4] = {};
+  const double* Sb = S ? S + (long long)b * ldS : nullptr;
+  for (int l0 = 0; l0 < nl; l0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e / GK, l = e % GK;
+      const int gi = i0 + r, gj = j0 + r, gl = l0 + l;
+      double s = 1.0;
+      if (Sb && gl < nl) s = Sb[gl];
+      xs[l][r] = (gi < ni && gl < nl) ? s * X[(long long)gi * nl + gl] : 0.0;
+      ys[l][r] = (gj < nj && gl < nl) ? Y[(long long)gj * nl + gl] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < GK; ++l) {
+      double xv[4], yv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = xs[l][ti + 16 * a];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) yv[a] = ys[l][tj + 16 * a];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
+    }
+    __syncthreads();
+  }
+  double* ob = out + (long long)b * out_bstride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int gi = i0 + ti + 16 * a;
+    if (gi >= ni) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gj = j0 + tj + 16 * c;
+      if (gj < nj) ob[(long long)gi * nj + gj] = alpha * acc[a][c];
+    }
+  }
+}
+
+// G_hat[iy][iz][kx] (pitch px, type T) = scale * D[iz][iy][kx]
+template <typename T>
+__global__ void k_store_ghat(const double* __restrict__ D, int kz, int ky, int kx, int px, double scale,
+                             T* __restrict__ g) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)kz * ky * kx;
+  if (idx >= tot) return;
+  const int x = int(idx % kx);
+  const int y = int((idx / kx) % ky);
+  const int z = int(idx / ((long long)kx * ky));
+  g[((long long)y * kz + z) * px + x] = T(scale * D[idx]);
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static void cosine_matrix(int K, std::vector<double>& C) {
+  // C[k][n] = w_n cos(pi n k / (K-1)), w_0 = w_{K-1} = 1, else 2 (DCT-I)
+  const long long M = 2LL * (K - 1);
+  C.assign((size_t)K * K, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int n = 0; n < K; ++n) {
+      const double wn = (n == 0 || n == K - 1) ? 1.0 : 2.0;
+      C[(size_t)k * K + n] = wn * unit_root((long long)n * k, M).c;
+    }
+}
+
+GreenScratch green_scratch_layout(int kz, int ky, int kx) {
+  GreenScratch s{};
+  const int kmax = std::max(kz, std::max(ky, kx));
+  std::vector<double> t, w;
+  double Tsplit;
+  lgf_quadrature(kmax - 1, t, w, &Tsplit);
+  const int J = int(t.size());
+  const int cols = J + kTailPairs;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  s.J = J;
+  s.cols = cols;
+  s.off_t = take(sizeof(double) * J);
+  s.off_w = take(sizeof(double) * J);
+  s.off_B = take(sizeof(double) * (size_t)kmax * J);
+  s.off_Az = take(sizeof(double) * (size_t)kz * cols);
+  s.off_Ay = take(sizeof(double) * (size_t)ky * cols);
+  s.off_Ax = take(sizeof(double) * (size_t)kx * cols);
+  s.off_Cx = take(sizeof(double) * (size_t)kx * kx);
+  s.off_Cy = take(sizeof(double) * (size_t)ky * ky);
+  s.off_Cz = take(sizeof(double) * (size_t)kz * kz);
+  const size_t vol = sizeof(double) * (size_t)kz * ky * kx;
+  s.off_G0 = take(vol);
+  s.off_G1 = take(vol);
+  s.bytes = off;
+  return s;
+}
+
+#define GCHECK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) return e_;               \
+  } while (0)
+
+template <typename T>
+hipError_t build_green_t(int kz, int ky, int kx, int px, double h, int mx, int my, int mz, void* ghat,
+                         void* scratch, hipStream_t st) {
+  const GreenScratch L = green_scratch_layout(kz, ky, kx);
+  char* base = static_cast<char*>(scratch);
+  auto P = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  const int kmax = std::max(kz, std::max(ky, kx));
+  std::vector<double> t, w;
+  double Tsplit;
+  lgf_quadrature(kmax - 1, t, w, &Tsplit);
+  const int J = L.J, cols = L.cols;
+  GCHECK(hipMemcpyAsync(P(L.off_t), t.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(L.off_w), w.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
+  std::vector<double> Cx, Cy, Cz;
+  cosine_matrix(kx, Cx);
+  cosine_matrix(ky, Cy);
+  cosine_matrix(kz, Cz);
+  GCHECK(hipMemcpyAsync(P(L.off_Cx), Cx.data(), sizeof(double) * Cx.size(), hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(L.off_Cy), Cy.data(), sizeof(double) * Cy.size(), hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(L.off_Cz), Cz.data(), sizeof(double) * Cz.size(), hipMemcpyHostToDevice, st));
+
+  hipLaunchKernelGGL(k_bessel_ive, dim3((J + 63) / 64), dim3(64), 0, st, P(L.off_t), J, kmax, P(L.off_B));
+  GCHECK(hipGetLastError());
+  const int ext[3] = {kz, ky, kx};
+  const size_t offA[3] = {L.off_Az, L.off_Ay, L.off_Ax};
+  for (int role = 0; role < 3; ++role) {
+    const long long n = (long long)ext[role] * cols;
+    hipLaunchKernelGGL(k_axis_table, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P(L.off_B),
+                       P(L.off_w), J, ext[role], role, Tsplit, P(offA[role]));
+    GCHECK(hipGetLastError());
+  }
+  // S[nz][ny][nx] = sum_col Az[nz][col] Ay[ny][col] Ax[nx][col] -> G0 (= -G1)
+  {
+    dim3 grid((kx + GT - 1) / GT, (ky + GT - 1) / GT, kz);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Ay), ky, P(L.off_Ax), kx, cols,
+                       P(L.off_Az), (long long)cols, 1.0, P(L.off_G0), (long long)ky * kx);
+    GCHECK(hipGetLastError());
+  }
+  // DCT-I along x: out[kx'][nz][ny] = sum_n Cx[kx'][n] G0[(nz,ny)][n]
+  {
+    const int a = kz * ky;
+    dim3 grid((a + GT - 1) / GT, (kx + GT - 1) / GT, 1);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Cx), kx, P(L.off_G0), a, kx,
+                       (const double*)nullptr, 0LL, 1.0, P(L.off_G1), 0LL);
+    GCHECK(hipGetLastError());
+  }
+  // along y: array (kx', nz, ny) -> out[ky'][kx'][nz]
+  {
+    const int a = kx * kz;
+    dim3 grid((a + GT - 1) / GT, (ky + GT - 1) / GT, 1);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Cy), ky, P(L.off_G1), a, ky,
+                       (const double*)nullptr, 0LL, 1.0, P(L.off_G0), 0LL);
+    GCHECK(hipGetLastError());
+  }
+  // along z: array (ky', kx', nz) -> out[kz'][ky'][kx']
+  {
+    const int a = ky * kx;
+    dim3 grid((a + GT - 1) / GT, (kz + GT - 1) / GT, 1);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Cz), kz, P(L.off_G0), a, kz,
+                       (const double*)nullptr, 0LL, 1.0, P(L.off_G1), 0LL);
+    GCHECK(hipGetLastError());
+  }
+  // G_hat = -(h^2 / (mx my mz)) * DCT(S)
+  {
+    const double scale = -(h * h) / (double(mx) * double(my) * double(mz));
+    const long long tot = (long long)kz * ky * kx;
+    hipLaunchKernelGGL((k_store_ghat<T>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
+                       P(L.off_G1), kz, ky, kx, px, scale, static_cast<T*>(ghat));
+    GCHECK(hipGetLastError());
+  }
+  // the host vectors above must outlive the copies
+  return hipStreamSynchronize(st);
+}
+
+template <typename T>
+__global__ void k_twiddles(const double* __restrict__ src, int n, cx<T>* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = cx<T>{T(src[2 * i]), T(src[2 * i + 1])};
+}
+
+template <typename T>
+hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
+  std::vector<double> tw(2 * (size_t)M);
+  for (int m = 0; m < M; ++m) {
+    const cs_pair r = unit_root(-(long long)m, M);  // exp(-2 pi i m / M)
+    tw[2 * m] = r.c;
+    tw[2 * m + 1] = r.s;
+  }
+  GCHECK(hipMemcpyAsync(scratch, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL((k_twiddles<T>), dim3((M + 255) / 256), dim3(256), 0, st,
+                     static_cast<const double*>(scratch), M, static_cast<cx<T>*>(dst));
+  GCHECK(hipGetLastError());
+  // the host vector must outlive the copy
+  GCHECK(hipStreamSynchronize(st));
+  return hipSuccess;
+}
+
+hipError_t build_green(bool f64, int kz, int ky, int kx, int px, double h, int mx, int my, int mz, void* ghat,
+                       void* scratch, hipStream_t st) {
+  hipError_t e = f64 ? build_green_t<double>(kz, ky, kx, px, h, mx, my, mz, ghat, scratch, st)
+                     : build_green_t<float>(kz, ky, kx, px, h, mx, my, mz, ghat, scratch, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t build_twiddles(bool f64, int M, void* dst, void* scratch, hipStream_t st) {
+  return f64 ? build_twiddles_t<double>(M, dst, scratch, st) : build_twiddles_t<float>(M, dst, scratch, st);
+}
+
+}  // namespace ups

@@ -1,0 +1,30 @@
+// Setup-time builders: the Green's spectrum octant and the twiddle tables.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <vector>
+
+namespace ups {
+
+// Byte offsets of the double-precision scratch arrays the builder uses
+// inside the caller's work buffer.
+struct GreenScratch {
+  int J, cols;
+  size_t off_t, off_w, off_B, off_Az, off_Ay, off_Ax, off_Cx, off_Cy, off_Cz, off_G0, off_G1;
+  size_t bytes;
+};
+
+GreenScratch green_scratch_layout(int kz, int ky, int kx);
+
+// Quadrature nodes t_j and weights w_j (dt folded in) on [0, T], and T.
+void lgf_quadrature(int n_max, std::vector<double>& t, std::vector<double>& w, double* T_out);
+
+// Ghat[iy][iz][kx] (pitch px) = h^2/(mx my mz) * DCT-I(G1) on the octant
+// kz x ky x kx = (mz/2+1) x (my/2+1) x (mx/2+1); waits for completion.
+hipError_t build_green(bool f64, int kz, int ky, int kx, int px, double h, int mx, int my, int mz,
+                       void* ghat, void* scratch, hipStream_t st);
+
+// dst[m] = exp(-2 pi i m / M), m < M, complex float or double; waits.
+hipError_t build_twiddles(bool f64, int M, void* dst, void* scratch, hipStream_t st);
+
+}  // namespace ups

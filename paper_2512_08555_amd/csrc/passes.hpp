@@ -1,0 +1,55 @@
+// The five FFT passes of the free-space convolution and their variant table.
+//
+// Data layout (all complex<T>, x-frequency fastest):
+//   W[c][z][y][kx]   z < Nz, y < My, kx < Kx = Mx/2+1, row pitch px >= Kx,
+//                    plane = My * px; the x pass fills rows y < Ny, the
+//                    y-forward pass expands each plane in place to My rows.
+//   Ghat[iy][iz][kx] octant iy <= My/2, iz <= Mz/2, same pitch px (real T).
+//   f, u             real T [c][Nz][Ny][Nx], contiguous.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+namespace ups {
+
+struct PassArgs {
+  int nx, ny, nz;        // source points per axis
+  int mx, my, mz;        // padded FFT lengths (even)
+  int kx;                // mx/2 + 1 stored x frequencies
+  int px;                // row pitch of W and Ghat (elements)
+  long long plane;       // my * px
+  long long comp_w;      // nz * plane: component stride of W
+  long long comp_f;      // nx * ny * nz: component stride of f and u
+  long long g_plane;     // (mz/2 + 1) * px: iy stride of Ghat
+  int ncomp;
+  const void* tw_x;      // exp(-2 pi i m / mx), m < mx
+  const void* tw_y;
+  const void* tw_z;
+  const void* ghat;
+};
+
+enum PassKind { PASS_XFWD = 0, PASS_YFWD = 1, PASS_ZCONV = 2, PASS_YINV = 3, PASS_XINV = 4, NUM_PASSES = 5 };
+
+// One compiled kernel variant of one pass for one (precision, length).
+struct PassVariant {
+  PassKind kind;
+  int is_f64;       // 1: double, 0: float
+  int length;       // mx for X passes, my for Y passes, mz for Z pass
+  int P, Q;         // line split: length (or length/2 for X passes) = P * Q
+  int tile;         // rows (X passes) or columns (Y, Z passes) per workgroup
+  int nch;          // LDS exchange chunks
+  int threads;      // workgroup size
+  int lds_bytes;
+  const char* name;
+  // enqueue on stream: in -> out (for in-place passes in == out == W)
+  void (*launch)(const PassArgs&, const void* in, void* out, hipStream_t);
+};
+
+const std::vector<PassVariant>& pass_variants();
+
+// helpers shared with the plan
+int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* gz);
+
+}  // namespace ups

@@ -1,0 +1,47 @@
+// Plan geometry and the opaque plan object behind ups_plan_t.
+#pragma once
+#include <cstddef>
+
+#include "../../include/ups.h"
+#include "passes.hpp"
+
+namespace ups {
+
+struct PlanGeom {
+  bool f64;
+  size_t elem;               // bytes of one real element
+  int nx, ny, nz;            // points
+  int mx, my, mz;            // padded lengths
+  int kx, oy, oz;            // stored x frequencies, octant extents in y and z
+  int px;                    // row pitch of W and G_hat (elements)
+  int ncomp;
+  double h;
+  long long plane, comp_w;   // W strides (complex elements)
+  size_t solve_work;         // bytes of W
+  size_t work_bytes;         // max(W, setup scratch)
+  size_t green_bytes;
+  size_t off_ghat, off_twx, off_twy, off_twz;
+};
+
+ups_status validate_problem(const ups_problem* p, PlanGeom* g);
+void plan_layout(PlanGeom& g);
+double model_bytes(const PlanGeom& g, int pass);
+const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name);
+PassArgs make_args(const PlanGeom& g, const void* green);
+ups_status check_device(int* dev_out);
+ups_status set_error(ups_status s, const char* msg);
+ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a,
+                         const void* f, void* u, void* work, hipStream_t st);
+
+}  // namespace ups
+
+struct ups_plan_s {
+  ups_problem prob;
+  ups::PlanGeom g;
+  const ups::PassVariant* var[5];
+  void* green = nullptr;
+  void* work = nullptr;
+  int device = 0;
+  bool ready = false;
+  ups::PassArgs args{};
+};

@@ -1,0 +1,178 @@
+"""Python face of libups: plans bound to torch device memory and streams.
+
+Arrays are torch tensors on the current HIP device, indexed [z, y, x] (or
+[c, z, y, x] for ncomp > 1), float64 for prec="f64" and float32 for "f32".
+Every numeric step runs in the library's HIP kernels; this module only
+allocates buffers with torch and passes pointers and the current stream.
+"""
+import ctypes as C
+
+import torch
+
+from . import _capi as capi
+
+PASS_NAMES = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_problem(shape, h, prec="f64", ncomp=1, pad=None):
+    """ups_problem for a grid of shape (nz, ny, nx) with isotropic spacing h."""
+    nz, ny, nx = (int(v) for v in shape)
+    p = capi.ups_problem()
+    capi.lib().ups_problem_init(C.byref(p))
+    p.n[0], p.n[1], p.n[2] = nx, ny, nz
+    for i in range(3):
+        p.h[i] = float(h)
+    p.prec = capi.UPS_F64 if prec == "f64" else capi.UPS_F32
+    p.ncomp = int(ncomp)
+    if pad is not None:
+        mz, my, mx = (int(v) for v in pad)
+        p.pad[0], p.pad[1], p.pad[2] = mx, my, mz
+    return p
+
+
+class Plan:
+    """A solve u = h^2 G1 * f on one grid (see include/ups.h).
+
+    Plan(shape, h, prec) validates and sizes the problem; setup() (called
+    by the constructor unless setup=False) allocates the green and work
+    buffers with torch on the current device and builds G_hat."""
+
+    def __init__(self, shape, h, prec="f64", ncomp=1, pad=None, setup=True, problem=None):
+        self.shape = tuple(int(v) for v in shape)
+        self.h = float(h)
+        self.prec = prec
+        self.ncomp = int(ncomp)
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        L = capi.lib()
+        self._prob = problem if problem is not None else make_problem(self.shape, h, prec, ncomp, pad)
+        handle = C.c_void_p()
+        capi.check(L.ups_plan_create(C.byref(self._prob), C.byref(handle)))
+        self._h = handle
+        gb, wb = C.c_size_t(), C.c_size_t()
+        capi.check(L.ups_plan_sizes(self._h, C.byref(gb), C.byref(wb)))
+        self.green_bytes, self.work_bytes = gb.value, wb.value
+        self.green = None
+        self.work = None
+        if setup:
+            self.setup()
+
+    # -- lifecycle --------------------------------------------------------------
+    def setup(self, device=None, stream=None):
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        self.green = torch.empty(self.green_bytes, dtype=torch.uint8, device=dev)
+        self.work = torch.empty(self.work_bytes, dtype=torch.uint8, device=dev)
+        capi.check(capi.lib().ups_plan_setup(self._h, C.c_void_p(self.green.data_ptr()), self.green_bytes,
+                                             C.c_void_p(self.work.data_ptr()), self.work_bytes,
+                                             _stream_handle(stream)))
+        return self
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().ups_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- solves -----------------------------------------------------------------
+    def _shape_io(self):
+        return self.shape if self.ncomp == 1 else (self.ncomp,) + self.shape
+
+    def _check(self, t, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if t.dtype != self.dtype or tuple(t.shape) != self._shape_io() or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s" % (name, self.dtype, self._shape_io()))
+
+    def empty_like_io(self):
+        return torch.empty(self._shape_io(), dtype=self.dtype, device=self.work.device)
+
+    def solve(self, f, out=None, stream=None):
+        """u = h^2 G1 * f (forward solve); out may be f (in place)."""
+        self._check(f, "f")
+        u = self.empty_like_io() if out is None else out
+        self._check(u, "out")
+        capi.check(capi.lib().ups_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                        _stream_handle(stream)))
+        return u
+
+    def adjoint(self, g, out=None, stream=None):
+        """grad_f = K^T grad_u through ups_solve_adjoint."""
+        self._check(g, "grad_u")
+        r = self.empty_like_io() if out is None else out
+        self._check(r, "out")
+        capi.check(capi.lib().ups_solve_adjoint(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(r.data_ptr()),
+                                                _stream_handle(stream)))
+        return r
+
+    def run_pass(self, k, f=None, u=None, stream=None):
+        """Enqueue pass k (0..4) alone on the bound work buffer."""
+        fi = C.c_void_p(f.data_ptr()) if f is not None else C.c_void_p(self.work.data_ptr())
+        uo = C.c_void_p(u.data_ptr()) if u is not None else C.c_void_p(self.work.data_ptr())
+        capi.check(capi.lib().ups_run_pass(self._h, int(k), fi, uo, _stream_handle(stream)))
+
+    # -- introspection ---------------------------------------------------------
+    def layout(self):
+        pitch, plane, comp = C.c_int(), C.c_longlong(), C.c_longlong()
+        goff, gplane = C.c_size_t(), C.c_longlong()
+        capi.check(capi.lib().ups_plan_layout(self._h, C.byref(pitch), C.byref(plane), C.byref(comp),
+                                              C.byref(goff), C.byref(gplane)))
+        return dict(pitch=pitch.value, plane=plane.value, comp_stride=comp.value,
+                    ghat_offset=goff.value, ghat_plane=gplane.value)
+
+    def kernel(self, k):
+        s = capi.lib().ups_plan_kernel(self._h, int(k))
+        return s.decode() if s else None
+
+    def set_kernel(self, k, name):
+        capi.check(capi.lib().ups_plan_set_kernel(self._h, int(k), name.encode()))
+
+    def model_bytes(self, k=-1):
+        return capi.lib().ups_plan_model_bytes(self._h, int(k))
+
+    @property
+    def padded(self):
+        p = self._prob
+        mx = p.pad[0] or 2 * p.n[0]
+        my = p.pad[1] or 2 * p.n[1]
+        mz = p.pad[2] or 2 * p.n[2]
+        return (mz, my, mx)
+
+    def ghat(self):
+        """Copy of G_hat (octant [iz, iy, kx], plan precision) read from the green
+        buffer, for inspection."""
+        lay = self.layout()
+        mz, my, mx = self.padded
+        oz, oy, kx = mz // 2 + 1, my // 2 + 1, mx // 2 + 1
+        esz = 8 if self.prec == "f64" else 4
+        n = oy * lay["ghat_plane"]
+        raw = self.green[lay["ghat_offset"]: lay["ghat_offset"] + n * esz].view(self.dtype)
+        g = raw.view(oy, oz, lay["pitch"])[:, :, :kx]
+        return g.permute(1, 0, 2).contiguous()
+
+    def work_complex(self):
+        """The work buffer viewed as complex [c][z][y][pitch] (plan precision)."""
+        lay = self.layout()
+        ct = torch.complex128 if self.prec == "f64" else torch.complex64
+        nz = self.shape[0]
+        n = self.ncomp * lay["comp_stride"]
+        esz = 16 if self.prec == "f64" else 8
+        w = self.work[: n * esz].view(ct)
+        my = lay["plane"] // lay["pitch"]
+        return w.view(self.ncomp, nz, my, lay["pitch"])
+
+
+def solve(f, h, prec=None, pad=None):
+    """One-shot solve of a [z, y, x] (or [c, z, y, x] with c = 3) tensor."""
+    prec = prec or ("f64" if f.dtype == torch.float64 else "f32")
+    ncomp = 1 if f.dim() == 3 else f.shape[0]
+    shape = tuple(f.shape[-3:])
+    return Plan(shape, h, prec, ncomp=ncomp, pad=pad).solve(f.contiguous())

@@ -1,0 +1,147 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/ups.h declares, validates problems and fails cleanly."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2512_08555_amd import _capi as capi
+from paper_2512_08555_amd.solver import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(capi.LIB_PATH):
+        pytest.skip("libups.so not built")
+    return capi.lib()
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ups.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ups_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    L = _lib_or_skip()
+    names = _declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in capi.SIGNATURES, "binding lacks " + n
+
+
+def test_abi_version_and_lengths():
+    L = _lib_or_skip()
+    assert L.ups_abi_version() == 1
+    for m in (32, 64, 128, 256, 512, 1024):
+        assert L.ups_supported_length(m, capi.UPS_F64) == 1
+        assert L.ups_supported_length(m, capi.UPS_F32) == 1
+    assert L.ups_supported_length(33, capi.UPS_F64) == 0
+    assert L.ups_supported_length(0, capi.UPS_F64) == 0
+
+
+def _create(p):
+    L = capi.lib()
+    h = C.c_void_p()
+    s = L.ups_plan_create(C.byref(p), C.byref(h))
+    return s, h, L.ups_last_error().decode()
+
+
+def test_validation_errors():
+    L = _lib_or_skip()
+    p = make_problem((32, 32, 32), 1 / 32)
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    L.ups_plan_destroy(h)
+
+    p = make_problem((32, 32, 1), 1 / 32)
+    s, h, msg = _create(p)
+    assert s == capi.UPS_ERR_INVALID_ARG and "n[0]" in msg and not h.value
+
+    p = make_problem((32, 32, 32), 1 / 32)
+    p.h[1] = 0.5
+    assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
+
+    p = make_problem((32, 32, 32), 1 / 32)
+    p.h[2] = -1.0
+    assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
+
+    p = make_problem((32, 32, 32), 1 / 32)
+    p.bc[1][0] = capi.UPS_BC_PER
+    s, _, msg = _create(p)
+    assert s == capi.UPS_ERR_UNSUPPORTED and "unbounded" in msg
+
+    p = make_problem((32, 32, 32), 1 / 32)
+    p.green = capi.UPS_GREEN_LGF4_MEHR
+    assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
+
+    p = make_problem((32, 32, 32), 1 / 32, ncomp=9)
+    assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
+
+    p = make_problem((20, 20, 20), 1 / 20, pad=(36, 40, 40))   # 36 < 2*20-2
+    assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
+    p = make_problem((20, 20, 20), 1 / 20, pad=(40, 40, 41))   # odd
+    assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
+    p = make_problem((20, 20, 20), 1 / 20)                      # 40: no kernel
+    assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
+    p = make_problem((20, 20, 20), 1 / 20, pad=(64, 64, 64))
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    L.ups_plan_destroy(h)
+
+    assert L.ups_plan_create(None, C.byref(C.c_void_p())) == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_plan_create(C.byref(p), None) == capi.UPS_ERR_INVALID_ARG
+
+
+def test_sizes_model_bytes_and_kernels():
+    L = _lib_or_skip()
+    p = make_problem((512, 512, 512), 1 / 512, prec="f32")
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    g, w = C.c_size_t(), C.c_size_t()
+    assert L.ups_plan_sizes(h, C.byref(g), C.byref(w)) == capi.UPS_OK
+    N = 512
+    # work holds W = N * 2N * pitch complex float, pitch >= N + 1
+    assert w.value >= N * 2 * N * (N + 1) * 8
+    assert g.value >= (N + 1) ** 3 * 4
+    # byte model: s [2 N^3 + 24 (N+1) N^2 + (N+1)^3], s = 4
+    ref = 4.0 * (2 * N ** 3 + 24 * (N + 1) * N ** 2 + (N + 1) ** 3)
+    assert abs(L.ups_plan_model_bytes(h, -1) - ref) < 1e-6 * ref
+    assert sum(L.ups_plan_model_bytes(h, k) for k in range(5)) == pytest.approx(ref)
+    assert L.ups_plan_model_bytes(h, 7) == 0.0
+    names = [L.ups_plan_kernel(h, k).decode() for k in range(5)]
+    assert names[0].startswith("xfwd_float") and names[2].startswith("zconv_float")
+    assert L.ups_plan_kernel(h, 5) is None
+    assert L.ups_plan_set_kernel(h, 2, b"nonexistent") == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_plan_set_kernel(h, 2, names[2].encode()) == capi.UPS_OK
+    L.ups_plan_destroy(h)
+
+
+def test_calls_before_setup_and_without_device_fail_cleanly():
+    L = _lib_or_skip()
+    p = make_problem((32, 32, 32), 1 / 32)
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    assert L.ups_solve(h, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
+    assert L.ups_solve_adjoint(h, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
+    assert L.ups_run_pass(h, 0, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
+    assert L.ups_run_pass(h, 9, None, None, None) == capi.UPS_ERR_INVALID_ARG
+    g, w = C.c_size_t(), C.c_size_t()
+    L.ups_plan_sizes(h, C.byref(g), C.byref(w))
+    # size and alignment checks come before any device access
+    assert L.ups_plan_setup(h, C.c_void_p(256), g.value - 1, C.c_void_p(1 << 20), w.value,
+                            None) == capi.UPS_ERR_WORKSPACE
+    assert L.ups_plan_setup(h, C.c_void_p(256), g.value, C.c_void_p(1 << 20), w.value - 1,
+                            None) == capi.UPS_ERR_WORKSPACE
+    assert L.ups_plan_setup(h, C.c_void_p(257), g.value, C.c_void_p(1 << 20), w.value,
+                            None) == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_plan_setup(h, None, g.value, C.c_void_p(1 << 20), w.value, None) == capi.UPS_ERR_INVALID_ARG
+    import torch
+    if not torch.cuda.is_available():
+        s = L.ups_plan_setup(h, C.c_void_p(256), g.value, C.c_void_p(1 << 20), w.value, None)
+        assert s == capi.UPS_ERR_DEVICE
+        assert "device" in L.ups_last_error().decode()
+    L.ups_plan_destroy(h)
