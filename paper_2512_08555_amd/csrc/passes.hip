@@ -14,6 +14,11 @@
 // elements of a row.  Y and Z passes (strided lines) put C adjacent columns
 // on consecutive lanes, thread index = c + C tl, so every wave reads and
 // writes C-element contiguous segments of several lines.
+//
+// LDS exchanges run in NCH phases, each over one group of rows (columns): a
+// thread keeps its line data in registers until its group's phase, so the
+// workgroup needs LDS for only RW/NCH rows (C/NCH columns) at a time and the
+// register peak stays at one line share per thread.
 #include "passes.hpp"
 #include "dft.hpp"
 
@@ -29,12 +34,25 @@ struct Split {
   static_assert(D1 * TL == Q && D3 * TL == P, "P must divide Q or Q divide P");
 };
 
-// per-thread spectrum of a column line: w[d3][k2] = X[k1 + P k2], k1 = tl + TL d3
+// per-thread spectrum of a line: w[d3][k2] = X[k1 + P k2], k1 = tl + TL d3
 template <typename T, int P, int Q>
 using ColSpec = cx<T>[Split<P, Q>::D3][Q];
 
+// Loads and stores at a wave-uniform base plus a 32-bit per-thread byte
+// offset, so addresses need one vector register instead of a 64-bit pair.
 template <typename T>
-__device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
+__device__ __forceinline__ cx<T> ld_at(const cx<T>* ubase, unsigned byte_off) {
+  return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(ubase) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) {
+  *reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(ubase) + byte_off) = v;
+}
+// twiddle table entry exp(-2 pi i idx / M)
+template <typename T>
+__device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, unsigned idx) {
+  return ld_at(tw, idx * unsigned(sizeof(cx<T>)));
+}
 
 template <typename T>
 __device__ __forceinline__ cx<T> zero_c() { return cx<T>{T(0), T(0)}; }
@@ -53,21 +71,27 @@ __device__ __forceinline__ void last_dft(cx<T>* v) {
 template <int P>
 constexpr int live_in() { return P % 2 == 0 ? P / 2 : P; }
 
+
 // ============================================================================
 // Pass 1: zero-pad + real-to-complex DFT along x (contiguous rows).
 // Row of nx reals, padded to mx = 2L, packed as z[m] = x[2m] + i x[2m+1]
 // (length L), transformed, then untangled:
 //   X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) w^k (Z[k] - conj Z[L-k]),  k <= L.
 // ============================================================================
-template <typename T, int P, int Q, int RW>
+template <int P, int Q>
+constexpr int xfwd_row_stride() {
+  constexpr int ys = P * (Q + 1), zs = P * Q + 1;
+  return (ys > zs ? ys : zs) | 1;
+}
+
+template <typename T, int P, int Q, int RW, int NCH>
 __global__ void __launch_bounds__((RW * Split<P, Q>::TL))
 k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
   using S = Split<P, Q>;
-  constexpr int L = S::L, TL = S::TL;
-  constexpr int YS = P * (Q + 1);
-  constexpr int ZS = L + 1;
-  constexpr int RS = (YS > ZS ? YS : ZS) | 1;
-  __shared__ cx<T> lds[RW * RS];
+  constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
+  constexpr int RS = xfwd_row_stride<P, Q>();
+  static_assert(RW % NCH == 0, "row groups");
+  __shared__ cx<T> lds[RG * RS];
 
   const int tid = threadIdx.x;
   const int tl = tid % TL, r = tid / TL;
@@ -80,14 +104,14 @@ k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
   const T* src = f + comp * a.comp_f + row * a.nx;
   cx<T>* dst = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);  // length mx = 2L
-  cx<T>* my = lds + r * RS;
+  cx<T>* my = lds + (r % RG) * RS;
   const int nx = a.nx;
   const bool even_nx = (nx & 1) == 0;
 
+  cx<T> v[S::D1][P];
   static_for<0, S::D1>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int q = tl + TL * d;
-    cx<T> v[P];
     static_for<0, live_in<P>()>([&](auto pp) {
       constexpr int p = decltype(pp)::value;
       const int m = q + Q * p;  // packed index: reals 2m, 2m+1
@@ -100,48 +124,63 @@ k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
           if (2 * m + 1 < nx) val.im = src[2 * m + 1];
         }
       }
-      v[p] = val;
+      v[d][p] = val;
     });
-    first_dft<P, -1>(v);
+    first_dft<P, -1>(v[d]);
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
-      v[k1] = cmul(v[k1], tw[2 * q * k1]);  // w_L^{q k1} = w_M^{2 q k1}
-    });
-    static_for<0, P>([&](auto kk) {
-      constexpr int k1 = decltype(kk)::value;
-      my[k1 * (Q + 1) + q] = v[k1];
+      v[d][k1] = cmul(v[d][k1], tw_at(tw, 2u * unsigned(q) * k1));  // w_L^{q k1} = w_M^{2 q k1}
     });
   });
-  __syncthreads();
-  ColSpec<T, P, Q> w;
-  static_for<0, S::D3>([&](auto dd) {
-    constexpr int d = decltype(dd)::value;
-    const int k1 = tl + TL * d;
-    static_for<0, Q>([&](auto qq) {
-      constexpr int q = decltype(qq)::value;
-      w[d][q] = my[k1 * (Q + 1) + q];
-    });
-    dft<Q, -1>(w[d]);
-  });
-  __syncthreads();
-  static_for<0, S::D3>([&](auto dd) {
-    constexpr int d = decltype(dd)::value;
-    const int k1 = tl + TL * d;
-    static_for<0, Q>([&](auto kk) {
-      constexpr int k2 = decltype(kk)::value;
-      my[k1 + P * k2] = w[d][k2];
-    });
-  });
-  __syncthreads();
-  if (valid) {
-    for (int k = tl; k <= L; k += TL) {
-      const cx<T> zk = my[k == L ? 0 : k];
-      const cx<T> zm = conj(my[k == 0 ? 0 : L - k]);
-      const cx<T> e = scale(zk + zm, T(0.5));
-      const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));  // (Z - conj Z')/(2i)
-      dst[k] = e + cmul(o, tw[k]);
+  static_for<0, NCH>([&](auto hh) {
+    constexpr int h = decltype(hh)::value;
+    const bool mine = r / RG == h;
+    if constexpr (h > 0) __syncthreads();
+    if (mine) {
+      static_for<0, S::D1>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int q = tl + TL * d;
+        static_for<0, P>([&](auto kk) {
+          constexpr int k1 = decltype(kk)::value;
+          my[k1 * (Q + 1) + q] = v[d][k1];
+        });
+      });
     }
-  }
+    __syncthreads();
+    ColSpec<T, P, Q> w;
+    if (mine) {
+      static_for<0, S::D3>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int k1 = tl + TL * d;
+        static_for<0, Q>([&](auto qq) {
+          constexpr int q = decltype(qq)::value;
+          w[d][q] = my[k1 * (Q + 1) + q];
+        });
+        dft<Q, -1>(w[d]);
+      });
+    }
+    __syncthreads();
+    if (mine) {
+      static_for<0, S::D3>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int k1 = tl + TL * d;
+        static_for<0, Q>([&](auto kk) {
+          constexpr int k2 = decltype(kk)::value;
+          my[k1 + P * k2] = w[d][k2];
+        });
+      });
+    }
+    __syncthreads();
+    if (mine && valid) {
+      for (int k = tl; k <= L; k += TL) {
+        const cx<T> zk = my[k == L ? 0 : k];
+        const cx<T> zm = conj(my[k == 0 ? 0 : L - k]);
+        const cx<T> e = scale(zk + zm, T(0.5));
+        const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));  // (Z - conj Z')/(2i)
+        dst[k] = e + cmul(o, tw_at(tw, unsigned(k)));
+      }
+    }
+  });
 }
 
 // ============================================================================
@@ -149,13 +188,17 @@ k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
 //   Z[k] = (X[k] + conj X[L-k]) + i w^{-k} (X[k] - conj X[L-k]),  k < L,
 // inverse length-L DFT of Z gives u[2m] + i u[2m+1] (unnormalised).
 // ============================================================================
-template <typename T, int P, int Q, int RW>
+template <int P, int Q>
+constexpr int xinv_row_stride() { return (Q * (P + 1)) | 1; }
+
+template <typename T, int P, int Q, int RW, int NCH>
 __global__ void __launch_bounds__((RW * Split<P, Q>::TL))
 k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
   using S = Split<P, Q>;
-  constexpr int L = S::L, TL = S::TL;
-  constexpr int VS = (Q * (P + 1)) | 1;
-  __shared__ cx<T> lds[RW * VS];
+  constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
+  constexpr int VS = xinv_row_stride<P, Q>();
+  static_assert(RW % NCH == 0, "row groups");
+  __shared__ cx<T> lds[RG * VS];
 
   const int tid = threadIdx.x;
   const int tl = tid % TL, r = tid / TL;
@@ -168,12 +211,12 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
   const cx<T>* src = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
   T* dst = u + comp * a.comp_f + row * a.nx;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);
-  cx<T>* my = lds + r * VS;
+  cx<T>* my = lds + (r % RG) * VS;
 
+  ColSpec<T, P, Q> w;
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + TL * d;
-    cx<T> w[Q];
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
       const int k = k1 + P * k2;
@@ -181,38 +224,54 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
       if (valid) {
         const cx<T> xk = src[k];
         const cx<T> xm = conj(src[L - k]);
-        zk = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw[k]));
+        zk = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw_at(tw, unsigned(k))));
       }
-      w[k2] = zk;
+      w[d][k2] = zk;
     });
-    dft<Q, +1>(w);
-    static_for<0, Q>([&](auto nn) {
+    dft<Q, +1>(w[d]);
+    static_for<1, Q>([&](auto nn) {
       constexpr int n2 = decltype(nn)::value;
-      const cx<T> t = (n2 == 0) ? w[n2] : cmulc(w[n2], tw[2 * n2 * k1]);
-      my[n2 * (P + 1) + k1] = t;
+      w[d][n2] = cmulc(w[d][n2], tw_at(tw, 2u * unsigned(k1) * n2));
     });
   });
-  __syncthreads();
   const int nx = a.nx;
   const bool even_nx = (nx & 1) == 0;
-  static_for<0, S::D1>([&](auto dd) {
-    constexpr int d = decltype(dd)::value;
-    const int n2 = tl + TL * d;
-    cx<T> v[P];
-    static_for<0, P>([&](auto kk) {
-      constexpr int k1 = decltype(kk)::value;
-      v[k1] = my[n2 * (P + 1) + k1];
-    });
-    last_dft<P, +1>(v);
-    if (valid) {
-      static_for<0, live_in<P>()>([&](auto nn) {
-        constexpr int n1 = decltype(nn)::value;
-        const int m = n2 + Q * n1;
-        if (even_nx) {
-          if (2 * m < nx) *reinterpret_cast<cx<T>*>(dst + 2 * m) = v[n1];
-        } else {
-          if (2 * m < nx) dst[2 * m] = v[n1].re;
-          if (2 * m + 1 < nx) dst[2 * m + 1] = v[n1].im;
+  static_for<0, NCH>([&](auto hh) {
+    constexpr int h = decltype(hh)::value;
+    const bool mine = r / RG == h;
+    if constexpr (h > 0) __syncthreads();
+    if (mine) {
+      static_for<0, S::D3>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int k1 = tl + TL * d;
+        static_for<0, Q>([&](auto nn) {
+          constexpr int n2 = decltype(nn)::value;
+          my[n2 * (P + 1) + k1] = w[d][n2];
+        });
+      });
+    }
+    __syncthreads();
+    if (mine) {
+      static_for<0, S::D1>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int n2 = tl + TL * d;
+        cx<T> v[P];
+        static_for<0, P>([&](auto kk) {
+          constexpr int k1 = decltype(kk)::value;
+          v[k1] = my[n2 * (P + 1) + k1];
+        });
+        last_dft<P, +1>(v);
+        if (valid) {
+          static_for<0, live_in<P>()>([&](auto nn) {
+            constexpr int n1 = decltype(nn)::value;
+            const int m = n2 + Q * n1;
+            if (even_nx) {
+              if (2 * m < nx) *reinterpret_cast<cx<T>*>(dst + 2 * m) = v[n1];
+            } else {
+              if (2 * m < nx) dst[2 * m] = v[n1].re;
+              if (2 * m + 1 < nx) dst[2 * m + 1] = v[n1].im;
+            }
+          });
         }
       });
     }
@@ -221,113 +280,131 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
 
 // ============================================================================
 // Column passes.  Thread (c, tl): c = column in the tile, tl = position on
-// the line.  The exchange between the two halves of the four-step goes
-// through LDS laid out [k1 - chunk][q (+1 pad)][c] in NCH chunks of k1.
+// the line.  A workgroup's lines start at a wave-uniform base (the tile's
+// first column); each element address is that base plus a multiple of the
+// line stride that is uniform across the wave plus one 32-bit per-thread
+// byte offset.  Exchanges go through LDS laid out [k1][q (+1 pad)][c'] for
+// the CG = C/NCH columns c' of the current phase.
 // ============================================================================
 
 // Forward step on lines of length M = P Q with inputs n < nlive (n = q + Q p,
-// p < P/2 when P is even).  base points at element 0 of column c; elements
-// are stride apart.  Returns, per thread, w[d3][k2] = X[k1 + P k2] with
+// p < P/2 when P is even).  ubase = element 0 of the tile's first column,
+// elements of a line `stride` apart.  Leaves w[d3][k2] = X[k1 + P k2],
 // k1 = tl + TL d3.
 template <typename T, int P, int Q, int C, int NCH>
-__device__ __forceinline__ void col_forward(const cx<T>* base, long long stride, bool valid, int nlive,
+__device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, bool valid, int nlive,
                                             const cx<T>* tw, cx<T>* lds, int c, int tl,
                                             ColSpec<T, P, Q>& w) {
   using S = Split<P, Q>;
-  constexpr int TL = S::TL, KC = P / NCH;
-  cx<T> v[S::D1][P];
+  constexpr int TL = S::TL, CG = C / NCH;
+  constexpr unsigned CB = sizeof(cx<T>);
+  // One register buffer holds the step-1 lines (D1 x P) and, after the
+  // exchange, the step-3 lines (D3 x Q): a thread's values are overwritten
+  // in place in its own phase, so both layouts share registers.
+  cx<T>* buf = &w[0][0];
   static_for<0, S::D1>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int q = tl + TL * d;
+    cx<T>* v = buf + d * P;
+    const unsigned toff = (unsigned(q) * unsigned(stride) + unsigned(c)) * CB;
     static_for<0, live_in<P>()>([&](auto pp) {
       constexpr int p = decltype(pp)::value;
-      const int n = q + Q * p;
-      v[d][p] = (valid && n < nlive) ? ldg(base + n * stride) : zero_c<T>();
+      const cx<T>* bp = ubase + (long long)(Q * p) * stride;
+      v[p] = (valid && q + Q * p < nlive) ? ld_at(bp, toff) : zero_c<T>();
     });
-    first_dft<P, -1>(v[d]);
+    first_dft<P, -1>(v);
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
-      v[d][k1] = cmul(v[d][k1], tw[q * k1]);
+      v[k1] = cmul(v[k1], tw_at(tw, unsigned(q) * k1));
     });
   });
+  const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {
     constexpr int h = decltype(hh)::value;
+    const bool mine = c / CG == h;
     if constexpr (h > 0) __syncthreads();
-    static_for<0, S::D1>([&](auto dd) {
-      constexpr int d = decltype(dd)::value;
-      const int q = tl + TL * d;
-      static_for<0, KC>([&](auto kk) {
-        constexpr int kr = decltype(kk)::value;
-        lds[(kr * (Q + 1) + q) * C + c] = v[d][h * KC + kr];
+    if (mine) {
+      static_for<0, S::D1>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int q = tl + TL * d;
+        static_for<0, P>([&](auto kk) {
+          constexpr int k1 = decltype(kk)::value;
+          lds[(k1 * (Q + 1) + q) * CG + cl] = buf[d * P + k1];
+        });
       });
-    });
+    }
     __syncthreads();
-    static_for<0, S::D3>([&](auto dd) {
-      constexpr int d = decltype(dd)::value;
-      const int k1 = tl + TL * d;
-      if (k1 / KC == h) {
-        const int kr = k1 - h * KC;
+    if (mine) {
+      static_for<0, S::D3>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int k1 = tl + TL * d;
         static_for<0, Q>([&](auto qq) {
           constexpr int q = decltype(qq)::value;
-          w[d][q] = lds[(kr * (Q + 1) + q) * C + c];
+          buf[d * Q + q] = lds[(k1 * (Q + 1) + q) * CG + cl];
         });
-      }
-    });
+      });
+    }
   });
   static_for<0, S::D3>([&](auto dd) { dft<Q, -1>(w[decltype(dd)::value]); });
 }
 
 // Inverse step: per thread w[d3][k2] = X[k1 + P k2] (k1 = tl + TL d3) in,
 // stores x[n2 + Q n1] for n1 < P/2 (n2 = tl + TL d1) where n < nkeep.
+// Starts with a barrier (the LDS may still be read by a previous phase).
 template <typename T, int P, int Q, int C, int NCH>
-__device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* base, long long stride,
-                                            bool valid, int nkeep, const cx<T>* tw, cx<T>* lds, int c,
-                                            int tl) {
+__device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, long long stride, bool valid,
+                                            int nkeep, const cx<T>* tw, cx<T>* lds, int c, int tl) {
   using S = Split<P, Q>;
-  constexpr int TL = S::TL, QC = Q / NCH;
+  constexpr int TL = S::TL, CG = C / NCH;
+  constexpr unsigned CB = sizeof(cx<T>);
+  cx<T>* buf = &w[0][0];
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + TL * d;
     dft<Q, +1>(w[d]);
     static_for<1, Q>([&](auto nn) {
       constexpr int n2 = decltype(nn)::value;
-      w[d][n2] = cmulc(w[d][n2], tw[n2 * k1]);
+      w[d][n2] = cmulc(w[d][n2], tw_at(tw, unsigned(k1) * n2));
     });
   });
-  cx<T> v[S::D1][P];
+  const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {
     constexpr int h = decltype(hh)::value;
+    const bool mine = c / CG == h;
     __syncthreads();
-    static_for<0, S::D3>([&](auto dd) {
-      constexpr int d = decltype(dd)::value;
-      const int k1 = tl + TL * d;
-      static_for<0, QC>([&](auto nn) {
-        constexpr int nr = decltype(nn)::value;
-        lds[(nr * (P + 1) + k1) * C + c] = w[d][h * QC + nr];
+    if (mine) {
+      static_for<0, S::D3>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int k1 = tl + TL * d;
+        static_for<0, Q>([&](auto nn) {
+          constexpr int n2 = decltype(nn)::value;
+          lds[(n2 * (P + 1) + k1) * CG + cl] = buf[d * Q + n2];
+        });
       });
-    });
+    }
     __syncthreads();
-    static_for<0, S::D1>([&](auto dd) {
-      constexpr int d = decltype(dd)::value;
-      const int n2 = tl + TL * d;
-      if (n2 / QC == h) {
-        const int nr = n2 - h * QC;
+    if (mine) {
+      static_for<0, S::D1>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        const int n2 = tl + TL * d;
         static_for<0, P>([&](auto kk) {
           constexpr int k1 = decltype(kk)::value;
-          v[d][k1] = lds[(nr * (P + 1) + k1) * C + c];
+          buf[d * P + k1] = lds[(n2 * (P + 1) + k1) * CG + cl];
         });
-      }
-    });
+      });
+    }
   });
   static_for<0, S::D1>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int n2 = tl + TL * d;
-    last_dft<P, +1>(v[d]);
+    cx<T>* v = buf + d * P;
+    last_dft<P, +1>(v);
     if (valid) {
+      const unsigned toff = (unsigned(n2) * unsigned(stride) + unsigned(c)) * CB;
       static_for<0, live_in<P>()>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
-        const int n = n2 + Q * n1;
-        if (n < nkeep) base[n * stride] = v[d][n1];
+        cx<T>* bp = ubase + (long long)(Q * n1) * stride;
+        if (n2 + Q * n1 < nkeep) st_at(bp, toff, v[n1]);
       });
     }
   });
@@ -335,8 +412,8 @@ __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* base, lo
 
 template <int P, int Q, int C, int NCH>
 constexpr int col_lds_elems() {
-  constexpr int a = (P / NCH) * (Q + 1) * C;
-  constexpr int b = (Q / NCH) * (P + 1) * C;
+  constexpr int a = P * (Q + 1) * (C / NCH);
+  constexpr int b = Q * (P + 1) * (C / NCH);
   return a > b ? a : b;
 }
 
@@ -345,23 +422,25 @@ template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL))
 k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
   using S = Split<P, Q>;
+  static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx = blockIdx.x * C + c;
+  const int kx0 = blockIdx.x * C;
   const int z = blockIdx.y, comp = blockIdx.z;
-  const bool valid = kx < a.kx;
-  cx<T>* base = W + comp * a.comp_w + z * a.plane + kx;
+  const bool valid = kx0 + c < a.kx;
+  cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH>(base, a.px, valid, a.ny, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH>(ubase, a.px, valid, a.ny, tw, lds, c, tl, w);
   if (valid) {
     static_for<0, S::D3>([&](auto dd) {
       constexpr int d = decltype(dd)::value;
       const int k1 = tl + S::TL * d;
+      const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(cx<T>));
       static_for<0, Q>([&](auto kk) {
         constexpr int k2 = decltype(kk)::value;
-        base[(long long)(k1 + P * k2) * a.px] = w[d][k2];
+        st_at(ubase + (long long)(P * k2) * a.px, toff, w[d][k2]);
       });
     });
   }
@@ -372,44 +451,76 @@ template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL))
 k_yinv(cx<T>* __restrict__ W, PassArgs a) {
   using S = Split<P, Q>;
+  static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx = blockIdx.x * C + c;
+  const int kx0 = blockIdx.x * C;
   const int z = blockIdx.y, comp = blockIdx.z;
-  const bool valid = kx < a.kx;
-  cx<T>* base = W + comp * a.comp_w + z * a.plane + kx;
+  const bool valid = kx0 + c < a.kx;
+  cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
+    const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(cx<T>));
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
-      w[d][k2] = valid ? ldg(base + (long long)(k1 + P * k2) * a.px) : zero_c<T>();
+      w[d][k2] = valid ? ld_at(ubase + (long long)(P * k2) * a.px, toff) : zero_c<T>();
     });
   });
-  col_inverse<T, P, Q, C, NCH>(w, base, a.px, valid, a.ny, tw, lds, c, tl);
+  col_inverse<T, P, Q, C, NCH>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
 }
 
-// Pass 3: along z, forward DFT (z < nz live), times Ghat, inverse DFT, keep
-// z < nz; in place.  One workgroup per (column tile, ky); the Ghat octant
-// line iy = min(ky, my - ky) is loaded once and applied to every component.
+// Pass 3 block order.  The workgroups that read the same G_hat octant line
+// (tile, iy) -- ky = iy and ky = my - iy, every component -- get linear
+// block ids 8 apart: consecutive blocks go round-robin to the eight XCDs,
+// so these land on one XCD, close in time, and share its L2.
+struct ZconvMap {
+  int tile, ky, comp;
+  bool active;
+};
+__device__ __forceinline__ ZconvMap zconv_map(unsigned b, int ntiles, int my, int ncomp) {
+  const int slots = 2 * ncomp;
+  const unsigned x = b % 8u, rest = b / 8u;
+  const int slot = int(rest % unsigned(slots));
+  const unsigned g = (rest / unsigned(slots)) * 8u + x;
+  const int oy = my / 2 + 1;
+  ZconvMap m;
+  m.active = g < unsigned(ntiles) * unsigned(oy);
+  const int iy = int(g / unsigned(ntiles));
+  m.tile = int(g % unsigned(ntiles));
+  const int side = slot & 1;
+  m.comp = slot >> 1;
+  m.ky = side ? my - iy : iy;
+  if (side && (iy == 0 || 2 * iy == my)) m.active = false;  // self-mirrored line
+  return m;
+}
+
+// Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
+// z < nz; in place.  One workgroup per (column tile, ky, component).
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL))
 k_zconv(cx<T>* __restrict__ W, PassArgs a) {
   using S = Split<P, Q>;
   constexpr int M = S::L;
+  static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
+  const int ntiles = (a.kx + C - 1) / C;
+  const ZconvMap mp = zconv_map(blockIdx.x, ntiles, a.my, a.ncomp);
+  if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx = blockIdx.x * C + c;
-  const int ky = blockIdx.y;
-  const bool valid = kx < a.kx;
+  const int kx0 = mp.tile * C;
+  const int ky = mp.ky;
+  const bool valid = kx0 + c < a.kx;
   const int iy = ky <= a.my - ky ? ky : a.my - ky;
-  const T* g = static_cast<const T*>(a.ghat) + iy * a.g_plane + kx;
+  const T* gbase = static_cast<const T*>(a.ghat) + iy * a.g_plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
-  T gv[S::D3][Q];
+  cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
+  ColSpec<T, P, Q> w;
+  col_forward<T, P, Q, C, NCH>(ubase, a.plane, valid, a.nz, tw, lds, c, tl, w);
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
@@ -417,23 +528,12 @@ k_zconv(cx<T>* __restrict__ W, PassArgs a) {
       constexpr int k2 = decltype(kk)::value;
       const int kz = k1 + P * k2;
       const int iz = kz <= M - kz ? kz : M - kz;
-      gv[d][k2] = valid ? g[(long long)iz * a.px] : T(0);
+      const unsigned goff = (unsigned(iz) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(T));
+      const T g = valid ? *reinterpret_cast<const T*>(reinterpret_cast<const char*>(gbase) + goff) : T(0);
+      w[d][k2] = scale(w[d][k2], g);
     });
   });
-  for (int comp = 0; comp < a.ncomp; ++comp) {
-    cx<T>* base = W + comp * a.comp_w + (long long)ky * a.px + kx;
-    ColSpec<T, P, Q> w;
-    if (comp > 0) __syncthreads();
-    col_forward<T, P, Q, C, NCH>(base, a.plane, valid, a.nz, tw, lds, c, tl, w);
-    static_for<0, S::D3>([&](auto dd) {
-      constexpr int d = decltype(dd)::value;
-      static_for<0, Q>([&](auto kk) {
-        constexpr int k2 = decltype(kk)::value;
-        w[d][k2] = scale(w[d][k2], gv[d][k2]);
-      });
-    });
-    col_inverse<T, P, Q, C, NCH>(w, base, a.plane, valid, a.nz, tw, lds, c, tl);
-  }
+  col_inverse<T, P, Q, C, NCH>(w, ubase, a.plane, valid, a.nz, tw, lds, c, tl);
 }
 
 // ============================================================================
@@ -441,16 +541,21 @@ k_zconv(cx<T>* __restrict__ W, PassArgs a) {
 // ============================================================================
 static inline int cdiv(long long a, long long b) { return int((a + b - 1) / b); }
 
-template <typename T, int P, int Q, int RW>
+static inline unsigned zconv_blocks(const PassArgs& a, int C) {
+  const long long groups = (long long)cdiv(a.kx, C) * (a.my / 2 + 1);
+  return unsigned(cdiv(groups, 8) * 8LL * 2 * a.ncomp);
+}
+
+template <typename T, int P, int Q, int RW, int NCH>
 void launch_xfwd(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
-  hipLaunchKernelGGL((k_xfwd<T, P, Q, RW>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_xfwd<T, P, Q, RW, NCH>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
                      static_cast<const T*>(in), static_cast<cx<T>*>(out), a);
 }
-template <typename T, int P, int Q, int RW>
+template <typename T, int P, int Q, int RW, int NCH>
 void launch_xinv(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
-  hipLaunchKernelGGL((k_xinv<T, P, Q, RW>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_xinv<T, P, Q, RW, NCH>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
                      static_cast<const cx<T>*>(in), static_cast<T*>(out), a);
 }
 template <typename T, int P, int Q, int C, int NCH>
@@ -467,65 +572,74 @@ void launch_yinv(const PassArgs& a, const void*, void* out, hipStream_t s) {
 }
 template <typename T, int P, int Q, int C, int NCH>
 void launch_zconv(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  dim3 grid(cdiv(a.kx, C), a.my, 1);
-  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), grid, dim3(C * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), dim3(zconv_blocks(a, C)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
 
 template <typename T>
 constexpr int is64() { return sizeof(T) == 8 ? 1 : 0; }
 
-#define UPS_STR2(x) #x
-#define UPS_STR(x) UPS_STR2(x)
+#define XF_VARIANT(T, P, Q, RW, NCH)                                                           \
+  PassVariant{PASS_XFWD, is64<T>(), 2 * P * Q, P, Q, RW, NCH, RW * Split<P, Q>::TL,            \
+              int(sizeof(cx<T>)) * (RW / NCH) * xfwd_row_stride<P, Q>(),                        \
+              "xfwd_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xfwd<T, P, Q, RW, NCH>}
+#define XI_VARIANT(T, P, Q, RW, NCH)                                                           \
+  PassVariant{PASS_XINV, is64<T>(), 2 * P * Q, P, Q, RW, NCH, RW * Split<P, Q>::TL,            \
+              int(sizeof(cx<T>)) * (RW / NCH) * xinv_row_stride<P, Q>(),                        \
+              "xinv_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xinv<T, P, Q, RW, NCH>}
+#define X_VARIANTS(T, P, Q, RW, NCH) XF_VARIANT(T, P, Q, RW, NCH), XI_VARIANT(T, P, Q, RW, NCH)
 
-#define X_VARIANTS(T, P, Q, RW)                                                                  \
-  PassVariant{PASS_XFWD, is64<T>(), 2 * P * Q, P, Q, RW, 1, RW * Split<P, Q>::TL,               \
-              int(sizeof(cx<T>)) * RW * ((P * (Q + 1) > P * Q + 1 ? P * (Q + 1) : P * Q + 1) | 1), \
-              "xfwd_" #T "_" #P "x" #Q "_r" #RW, &launch_xfwd<T, P, Q, RW>},                     \
-  PassVariant{PASS_XINV, is64<T>(), 2 * P * Q, P, Q, RW, 1, RW * Split<P, Q>::TL,               \
-              int(sizeof(cx<T>)) * RW * ((Q * (P + 1)) | 1),                                     \
-              "xinv_" #T "_" #P "x" #Q "_r" #RW, &launch_xinv<T, P, Q, RW>}
+#define COL_VARIANT(KIND, kname, T, P, Q, C, NCH)                                              \
+  PassVariant{KIND, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,                       \
+              int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                               \
+              #kname "_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_##kname<T, P, Q, C, NCH>}
+#define COL_VARIANTS(T, P, Q, C, NCH)                                                          \
+  COL_VARIANT(PASS_YFWD, yfwd, T, P, Q, C, NCH), COL_VARIANT(PASS_ZCONV, zconv, T, P, Q, C, NCH), \
+      COL_VARIANT(PASS_YINV, yinv, T, P, Q, C, NCH)
 
-#define COL_VARIANTS(T, P, Q, C, NCH)                                                         \
-  PassVariant{PASS_YFWD, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,                \
-              int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                             \
-              "yfwd_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_yfwd<T, P, Q, C, NCH>},     \
-  PassVariant{PASS_ZCONV, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,               \
-              int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                             \
-              "zconv_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_zconv<T, P, Q, C, NCH>},   \
-  PassVariant{PASS_YINV, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,                \
-              int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                             \
-              "yinv_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_yinv<T, P, Q, C, NCH>}
-
+// The first variant listed for a (pass, precision, length) is the default
+// (ordered by measured time on MI355X for the 256^3 and 512^3 grids).
+#define XF(T, P, Q, RW, NCH) XF_VARIANT(T, P, Q, RW, NCH)
+#define XI(T, P, Q, RW, NCH) XI_VARIANT(T, P, Q, RW, NCH)
+#define YF(T, P, Q, C, NCH) COL_VARIANT(PASS_YFWD, yfwd, T, P, Q, C, NCH)
+#define ZC(T, P, Q, C, NCH) COL_VARIANT(PASS_ZCONV, zconv, T, P, Q, C, NCH)
+#define YI(T, P, Q, C, NCH) COL_VARIANT(PASS_YINV, yinv, T, P, Q, C, NCH)
 const std::vector<PassVariant>& pass_variants() {
   static const std::vector<PassVariant> table = {
       // ---- float ----
-      X_VARIANTS(float, 4, 4, 16),      // mx = 32
-      X_VARIANTS(float, 4, 8, 16),      // mx = 64
-      X_VARIANTS(float, 8, 8, 16),      // mx = 128
-      X_VARIANTS(float, 8, 16, 16),     // mx = 256
-      X_VARIANTS(float, 16, 16, 16),    // mx = 512
-      X_VARIANTS(float, 16, 32, 16),    // mx = 1024
+      X_VARIANTS(float, 4, 4, 16, 1),       // mx = 32
+      X_VARIANTS(float, 4, 8, 16, 1),       // mx = 64
+      X_VARIANTS(float, 8, 8, 16, 2),       // mx = 128
+      X_VARIANTS(float, 8, 16, 16, 2),      // mx = 256
+      X_VARIANTS(float, 16, 16, 16, 2),     // mx = 512
+      XF(float, 16, 32, 16, 2), XF(float, 16, 32, 8, 2), XF(float, 16, 32, 16, 4),   // mx = 1024
+      XI(float, 16, 32, 8, 2), XI(float, 16, 32, 16, 2), XI(float, 16, 32, 16, 4),
       COL_VARIANTS(float, 4, 8, 16, 1),     // 32
       COL_VARIANTS(float, 8, 8, 16, 1),     // 64
-      COL_VARIANTS(float, 8, 16, 16, 1),    // 128
-      COL_VARIANTS(float, 16, 16, 16, 1),   // 256
-      COL_VARIANTS(float, 16, 32, 16, 1),   // 512
-      COL_VARIANTS(float, 32, 32, 16, 2),   // 1024
-      COL_VARIANTS(float, 32, 32, 8, 1),    // 1024
+      COL_VARIANTS(float, 8, 16, 16, 2),    // 128
+      COL_VARIANTS(float, 16, 16, 16, 2),   // 256
+      COL_VARIANTS(float, 16, 32, 16, 2),   // 512
+      YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
+      ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
+      YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2), YI(float, 32, 32, 16, 4),
       // ---- double ----
-      X_VARIANTS(double, 4, 4, 8),
-      X_VARIANTS(double, 4, 8, 8),
-      X_VARIANTS(double, 8, 8, 8),
-      X_VARIANTS(double, 8, 16, 8),
-      X_VARIANTS(double, 16, 16, 8),
-      X_VARIANTS(double, 16, 32, 8),
+      X_VARIANTS(double, 4, 4, 8, 1),
+      X_VARIANTS(double, 4, 8, 8, 1),
+      X_VARIANTS(double, 8, 8, 8, 2),
+      X_VARIANTS(double, 8, 16, 8, 2),
+      X_VARIANTS(double, 16, 16, 8, 2),
+      XF(double, 16, 32, 8, 2), XF(double, 16, 32, 8, 4),
+      XI(double, 16, 32, 8, 2), XI(double, 16, 32, 8, 4),
       COL_VARIANTS(double, 4, 8, 8, 1),
       COL_VARIANTS(double, 8, 8, 8, 1),
-      COL_VARIANTS(double, 8, 16, 8, 1),
-      COL_VARIANTS(double, 16, 16, 8, 1),
-      COL_VARIANTS(double, 16, 32, 8, 1),
-      COL_VARIANTS(double, 32, 32, 8, 2),
+      COL_VARIANTS(double, 8, 16, 8, 2),
+      COL_VARIANTS(double, 16, 16, 8, 2),
+      YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
+      ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
+      YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
+      YF(double, 32, 32, 8, 2), YF(double, 32, 32, 8, 4),   // 1024
+      ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
+      YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
   };
   return table;
 }
@@ -539,7 +653,7 @@ int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* g
     case PASS_YINV:
       *gx = cdiv(a.kx, v.tile); *gy = a.nz; *gz = a.ncomp; break;
     default:
-      *gx = cdiv(a.kx, v.tile); *gy = a.my; *gz = 1; break;
+      *gx = int(zconv_blocks(a, v.tile)); *gy = 1; *gz = 1; break;
   }
   return (*gx) * (*gy) * (*gz);
 }
