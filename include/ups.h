@@ -163,8 +163,50 @@ ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long l
  * and of the whole solve for pass = -1.  Returns 0 on a bad argument. */
 double ups_plan_model_bytes(ups_plan_t plan, int pass);
 
+/* Time every compiled kernel variant of each pass on this plan's bound
+ * buffers (HIP events on `stream`; the work buffer's contents are
+ * overwritten) and keep the fastest.  Variants beyond the first are skipped
+ * once `budget_ms` of kernel time is spent.  The choices go to a process-wide
+ * cache used by later plans and batches of the same (pass, precision,
+ * padded length); with the environment variable UPS_TUNE_CACHE set to a
+ * file path the cache is loaded from and saved to that JSON file.  Waits for
+ * the stream.  Errors: STATE (setup not done), DEVICE. */
+ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms);
+
 /* Release the host-side plan.  Device buffers stay with the caller. */
 ups_status ups_plan_destroy(ups_plan_t plan);
+
+/* ---- batches ------------------------------------------------------------
+ * A batch runs `count` independent problems (any shapes, precisions and
+ * component counts; at most 200) as ONE hipGraph launch: for each of the
+ * five passes the problems sharing a compiled kernel run in one grouped
+ * launch, the grouped launches of a pass are parallel graph branches, and
+ * the passes follow each other.  Results equal those of ups_solve on each
+ * problem with the same kernel variants. */
+
+/* Validate every problem and lay out the batch (host only).  Errors as
+ * ups_plan_create for the first failing problem; UNSUPPORTED above 200. */
+ups_status ups_batch_create(const ups_problem* probs, int count, ups_batch_t* out);
+
+/* Bytes of the caller's buffers: green (every G_hat and twiddle table plus
+ * the launch tables; persistent) and work (every problem's scratch). */
+ups_status ups_batch_sizes(ups_batch_t batch, size_t* green_bytes, size_t* work_bytes);
+
+/* Build every G_hat and the launch tables, capture the graph; waits for
+ * `stream`.  Errors: INVALID_ARG, WORKSPACE, DEVICE, STATE (called twice). */
+ups_status ups_batch_setup(ups_batch_t batch, void* green, size_t green_bytes, void* work,
+                           size_t work_bytes, void* stream);
+
+/* Solve every problem: f[i], u[i] are device arrays laid out as for
+ * ups_solve on problem i (u[i] may equal f[i]).  The pointer arrays are host
+ * arrays read during the call; one small kernel stores them on the device,
+ * then the graph is launched on `stream`. */
+ups_status ups_batch_solve(ups_batch_t batch, const void* const* f, void* const* u, void* stream);
+
+/* Number of grouped launches the batch uses for pass 0..4. */
+int ups_batch_launches(ups_batch_t batch, int pass);
+
+ups_status ups_batch_destroy(ups_batch_t batch);
 
 #ifdef __cplusplus
 }

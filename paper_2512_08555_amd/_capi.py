@@ -59,6 +59,13 @@ SIGNATURES = {
                                   C.POINTER(C.c_longlong), C.POINTER(C.c_size_t), C.POINTER(C.c_longlong)]),
     "ups_plan_model_bytes": (C.c_double, [C.c_void_p, C.c_int]),
     "ups_plan_destroy": (C.c_int, [C.c_void_p]),
+    "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    "ups_batch_create": (C.c_int, [C.POINTER(ups_problem), C.c_int, C.POINTER(C.c_void_p)]),
+    "ups_batch_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "ups_batch_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ups_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "ups_batch_launches": (C.c_int, [C.c_void_p, C.c_int]),
+    "ups_batch_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None

@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libups.so")
 OBJ = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["passes.hip", "green.hip", "capi.cpp"]
+SOURCES = ["passes_f32.hip", "passes_f32m.hip", "passes_f64.hip", "passes.cpp", "green.hip", "capi.cpp", "batch.cpp",
+           "autotune.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,155 @@
+// Autotuner: per (pass, precision, padded length), time every compiled
+// kernel variant on the plan's own buffers with HIP events and keep the
+// fastest.  Choices live in a process-wide cache that new plans and batches
+// consult; with UPS_TUNE_CACHE=<path> the cache is read from and written to
+// that JSON file ({"zconv/f32/1024": "zconv_float_32x32_c8_h2", ...}).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ups.h"
+#include "passes.hpp"
+#include "plan.hpp"
+
+using namespace ups;
+
+namespace {
+
+const char* kKindName[5] = {"xfwd", "yfwd", "zconv", "yinv", "xinv"};
+const PassKind kKinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
+
+std::mutex g_mu;
+std::map<std::string, std::string> g_cache;
+bool g_loaded = false;
+
+std::string key_of(PassKind kind, bool f64, int length) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "%s/%s/%d", kKindName[int(kind)], f64 ? "f64" : "f32", length);
+  return buf;
+}
+
+// minimal reader for a flat {"key": "value", ...} object
+void load_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = std::getenv("UPS_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream in(path);
+  if (!in) return;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string s = ss.str();
+  size_t i = 0;
+  auto next_str = [&](std::string& out) -> bool {
+    size_t a = s.find('"', i);
+    if (a == std::string::npos) return false;
+    size_t b = s.find('"', a + 1);
+    if (b == std::string::npos) return false;
+    out = s.substr(a + 1, b - a - 1);
+    i = b + 1;
+    return true;
+  };
+  std::string k, v;
+  while (next_str(k) && next_str(v)) g_cache[k] = v;
+}
+
+void save_locked() {
+  const char* path = std::getenv("UPS_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream out(path);
+  if (!out) return;
+  out << "{\n";
+  size_t n = 0;
+  for (const auto& kv : g_cache) {
+    out << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++n < g_cache.size() ? ",\n" : "\n");
+  }
+  out << "}\n";
+}
+
+}  // namespace
+
+namespace ups {
+
+// The variant a new plan uses: the cached tuning result if any, else the
+// table default.
+const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom&) {
+  std::string name;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    auto it = g_cache.find(key_of(kind, f64, length));
+    if (it != g_cache.end()) name = it->second;
+  }
+  if (!name.empty()) {
+    const PassVariant* v = find_variant(kind, f64, length, name.c_str());
+    if (v) return v;
+  }
+  return find_variant(kind, f64, length, nullptr);
+}
+
+}  // namespace ups
+
+extern "C" {
+
+ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
+  if (!plan) return set_error(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan->ready) return set_error(UPS_ERR_STATE, "ups_plan_setup has not completed on this plan");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PlanGeom& g = plan->g;
+  const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_error(UPS_ERR_DEVICE, "hipEventCreate failed");
+  // passes 0 and 4 read/write a real array: the work buffer stands in for
+  // f and u (timing does not depend on the values)
+  void* work = plan->work;
+  double spent = 0.0;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+    std::vector<const PassVariant*> cands;
+    for (const PassVariant& v : pass_variants())
+      if (v.kind == kKinds[k] && v.is_f64 == (g.f64 ? 1 : 0) && v.length == len[k]) cands.push_back(&v);
+    const PassVariant* best = plan->var[k];
+    float best_ms = 1e30f;
+    for (const PassVariant* v : cands) {
+      if (spent > budget_ms && v != plan->var[k]) continue;
+      const int reps = 5;
+      v->launch(plan->args, work, work, st);  // warm-up
+      err = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && err == hipSuccess; ++r) v->launch(plan->args, work, work, st);
+      if (err == hipSuccess) err = hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      ms /= reps;
+      spent += ms * (reps + 1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    plan->var[k] = best;
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    g_cache[key_of(kKinds[k], g.f64, len[k])] = best->name;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(err));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    save_locked();
+  }
+  return set_error(UPS_OK, "");
+}
+
+}  // extern "C"

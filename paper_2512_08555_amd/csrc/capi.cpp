@@ -236,7 +236,7 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   p->prob = *prob;
   p->g = g;
   for (int i = 0; i < 5; ++i) {
-    p->var[i] = find_variant(kinds[i], g.f64, len[i], nullptr);
+    p->var[i] = tuned_variant(kinds[i], g.f64, len[i], g);
     if (!p->var[i]) {
       delete p;
       return fail(UPS_ERR_UNSUPPORTED, "no kernel for pass %d at length %d", i, len[i]);

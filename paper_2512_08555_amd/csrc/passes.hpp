@@ -30,6 +30,24 @@ struct PassArgs {
   const void* ghat;
 };
 
+// One problem of a grouped launch (many problems, one pass, one kernel).
+// in/out are the pass's fixed buffers; io_in/io_out >= 0 take the pointer
+// from GroupArgs::io instead (the caller's f and u, set per solve).
+struct GroupEntry {
+  PassArgs a;
+  const void* in;
+  void* out;
+  int io_in, io_out;
+  unsigned block0;   // first block of this problem (a multiple of 8)
+  unsigned nblocks;
+};
+
+struct GroupArgs {
+  const GroupEntry* ents;        // device table
+  const unsigned short* bmap;    // block -> entry index
+  const void* const* io;         // device table of caller pointers
+};
+
 enum PassKind { PASS_XFWD = 0, PASS_YFWD = 1, PASS_ZCONV = 2, PASS_YINV = 3, PASS_XINV = 4, NUM_PASSES = 5 };
 
 // One compiled kernel variant of one pass for one (precision, length).
@@ -45,6 +63,8 @@ struct PassVariant {
   const char* name;
   // enqueue on stream: in -> out (for in-place passes in == out == W)
   void (*launch)(const PassArgs&, const void* in, void* out, hipStream_t);
+  // enqueue one grouped launch of nblocks blocks
+  void (*launch_grouped)(const GroupArgs&, unsigned nblocks, hipStream_t);
 };
 
 const std::vector<PassVariant>& pass_variants();

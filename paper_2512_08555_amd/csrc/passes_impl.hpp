@@ -19,19 +19,24 @@
 // thread keeps its line data in registers until its group's phase, so the
 // workgroup needs LDS for only RW/NCH rows (C/NCH columns) at a time and the
 // register peak stays at one line share per thread.
+#pragma once
 #include "passes.hpp"
 #include "dft.hpp"
 
 namespace ups {
 
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// Line of length L = P Q over TL = gcd(P, Q) threads: each thread runs
+// D1 = Q/TL DFTs of length P, then D3 = P/TL DFTs of length Q, and holds
+// E = D1 P = D3 Q values.
 template <int P, int Q>
 struct Split {
-  static constexpr int E = P > Q ? P : Q;
   static constexpr int L = P * Q;
-  static constexpr int TL = L / E;   // threads per line
-  static constexpr int D1 = Q / TL;  // P-DFTs per thread
-  static constexpr int D3 = P / TL;  // Q-DFTs per thread
-  static_assert(D1 * TL == Q && D3 * TL == P, "P must divide Q or Q divide P");
+  static constexpr int TL = cgcd(P, Q);  // threads per line
+  static constexpr int D1 = Q / TL;      // P-DFTs per thread
+  static constexpr int D3 = P / TL;      // Q-DFTs per thread
+  static constexpr int E = D1 * P;       // values per thread
 };
 
 // per-thread spectrum of a line: w[d3][k2] = X[k1 + P k2], k1 = tl + TL d3
@@ -85,8 +90,8 @@ constexpr int xfwd_row_stride() {
 }
 
 template <typename T, int P, int Q, int RW, int NCH>
-__global__ void __launch_bounds__((RW * Split<P, Q>::TL))
-k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
+__device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __restrict__ W, const PassArgs& a,
+                                          unsigned bx, unsigned by) {
   using S = Split<P, Q>;
   constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
   constexpr int RS = xfwd_row_stride<P, Q>();
@@ -95,37 +100,45 @@ k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
 
   const int tid = threadIdx.x;
   const int tl = tid % TL, r = tid / TL;
-  const long long row = (long long)blockIdx.x * RW + r;
-  const int comp = blockIdx.y;
+  const long long row = (long long)bx * RW + r;
+  const int comp = int(by);
   const long long nrows = (long long)a.ny * a.nz;
   const bool valid = row < nrows;
-  const int y = valid ? int(row % a.ny) : 0;
-  const int z = valid ? int(row / a.ny) : 0;
-  const T* src = f + comp * a.comp_f + row * a.nx;
+  const long long rowc = valid ? row : nrows - 1;  // in-bounds row for the loads
+  const int y = int(rowc % a.ny);
+  const int z = int(rowc / a.ny);
+  const T* src = f + comp * a.comp_f + rowc * a.nx;
   cx<T>* dst = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);  // length mx = 2L
   cx<T>* my = lds + (r % RG) * RS;
   const int nx = a.nx;
   const bool even_nx = (nx & 1) == 0;
+  // every loaded pair 2m, 2m+1 (m < Q live_in<P>) lies inside the row
+  const bool full = even_nx && nx >= 2 * Q * live_in<P>();
 
   cx<T> v[S::D1][P];
   static_for<0, S::D1>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int q = tl + TL * d;
-    static_for<0, live_in<P>()>([&](auto pp) {
-      constexpr int p = decltype(pp)::value;
-      const int m = q + Q * p;  // packed index: reals 2m, 2m+1
-      cx<T> val = zero_c<T>();
-      if (valid) {
+    if (full) {
+      static_for<0, live_in<P>()>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        v[d][p] = *reinterpret_cast<const cx<T>*>(src + 2 * (q + Q * p));
+      });
+    } else {
+      static_for<0, live_in<P>()>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        const int m = q + Q * p;  // packed index: reals 2m, 2m+1
+        cx<T> val = zero_c<T>();
         if (even_nx) {
           if (2 * m < nx) val = *reinterpret_cast<const cx<T>*>(src + 2 * m);
         } else {
           if (2 * m < nx) val.re = src[2 * m];
           if (2 * m + 1 < nx) val.im = src[2 * m + 1];
         }
-      }
-      v[d][p] = val;
-    });
+        v[d][p] = val;
+      });
+    }
     first_dft<P, -1>(v[d]);
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
@@ -172,13 +185,19 @@ k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
     }
     __syncthreads();
     if (mine && valid) {
-      for (int k = tl; k <= L; k += TL) {
-        const cx<T> zk = my[k == L ? 0 : k];
-        const cx<T> zm = conj(my[k == 0 ? 0 : L - k]);
-        const cx<T> e = scale(zk + zm, T(0.5));
-        const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));  // (Z - conj Z')/(2i)
-        dst[k] = e + cmul(o, tw_at(tw, unsigned(k)));
-      }
+      // k = tl + TL i for i < L/TL, then k = L on lane tl = 0
+      static_for<0, L / TL + 1>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const int k = tl + TL * i;
+        if (i < L / TL || tl == 0) {
+          const int kk = i < L / TL ? k : L;
+          const cx<T> zk = my[kk == L ? 0 : kk];
+          const cx<T> zm = conj(my[kk == 0 ? 0 : L - kk]);
+          const cx<T> e = scale(zk + zm, T(0.5));
+          const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));  // (Z - conj Z')/(2i)
+          dst[kk] = e + cmul(o, tw_at(tw, unsigned(kk)));
+        }
+      });
     }
   });
 }
@@ -192,8 +211,8 @@ template <int P, int Q>
 constexpr int xinv_row_stride() { return (Q * (P + 1)) | 1; }
 
 template <typename T, int P, int Q, int RW, int NCH>
-__global__ void __launch_bounds__((RW * Split<P, Q>::TL))
-k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
+__device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __restrict__ u, const PassArgs& a,
+                                          unsigned bx, unsigned by) {
   using S = Split<P, Q>;
   constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
   constexpr int VS = xinv_row_stride<P, Q>();
@@ -202,12 +221,13 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
 
   const int tid = threadIdx.x;
   const int tl = tid % TL, r = tid / TL;
-  const long long row = (long long)blockIdx.x * RW + r;
-  const int comp = blockIdx.y;
+  const long long row = (long long)bx * RW + r;
+  const int comp = int(by);
   const long long nrows = (long long)a.ny * a.nz;
   const bool valid = row < nrows;
-  const int y = valid ? int(row % a.ny) : 0;
-  const int z = valid ? int(row / a.ny) : 0;
+  const long long rowc = valid ? row : nrows - 1;  // in-bounds row for the loads
+  const int y = int(rowc % a.ny);
+  const int z = int(rowc / a.ny);
   const cx<T>* src = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
   T* dst = u + comp * a.comp_f + row * a.nx;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);
@@ -220,13 +240,9 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
       const int k = k1 + P * k2;
-      cx<T> zk = zero_c<T>();
-      if (valid) {
-        const cx<T> xk = src[k];
-        const cx<T> xm = conj(src[L - k]);
-        zk = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw_at(tw, unsigned(k))));
-      }
-      w[d][k2] = zk;
+      const cx<T> xk = src[k];
+      const cx<T> xm = conj(src[L - k]);
+      w[d][k2] = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw_at(tw, unsigned(k))));
     });
     dft<Q, +1>(w[d]);
     static_for<1, Q>([&](auto nn) {
@@ -236,6 +252,8 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
   });
   const int nx = a.nx;
   const bool even_nx = (nx & 1) == 0;
+  // every stored pair 2m, 2m+1 (m < Q live_in<P>) lies inside the row
+  const bool full = even_nx && nx >= 2 * Q * live_in<P>();
   static_for<0, NCH>([&](auto hh) {
     constexpr int h = decltype(hh)::value;
     const bool mine = r / RG == h;
@@ -262,16 +280,23 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
         });
         last_dft<P, +1>(v);
         if (valid) {
-          static_for<0, live_in<P>()>([&](auto nn) {
-            constexpr int n1 = decltype(nn)::value;
-            const int m = n2 + Q * n1;
-            if (even_nx) {
-              if (2 * m < nx) *reinterpret_cast<cx<T>*>(dst + 2 * m) = v[n1];
-            } else {
-              if (2 * m < nx) dst[2 * m] = v[n1].re;
-              if (2 * m + 1 < nx) dst[2 * m + 1] = v[n1].im;
-            }
-          });
+          if (full) {
+            static_for<0, live_in<P>()>([&](auto nn) {
+              constexpr int n1 = decltype(nn)::value;
+              *reinterpret_cast<cx<T>*>(dst + 2 * (n2 + Q * n1)) = v[n1];
+            });
+          } else {
+            static_for<0, live_in<P>()>([&](auto nn) {
+              constexpr int n1 = decltype(nn)::value;
+              const int m = n2 + Q * n1;
+              if (even_nx) {
+                if (2 * m < nx) *reinterpret_cast<cx<T>*>(dst + 2 * m) = v[n1];
+              } else {
+                if (2 * m < nx) dst[2 * m] = v[n1].re;
+                if (2 * m + 1 < nx) dst[2 * m + 1] = v[n1].im;
+              }
+            });
+          }
         }
       });
     }
@@ -292,7 +317,7 @@ k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
 // elements of a line `stride` apart.  Leaves w[d3][k2] = X[k1 + P k2],
 // k1 = tl + TL d3.
 template <typename T, int P, int Q, int C, int NCH>
-__device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, bool valid, int nlive,
+__device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, int cload, int nlive,
                                             const cx<T>* tw, cx<T>* lds, int c, int tl,
                                             ColSpec<T, P, Q>& w) {
   using S = Split<P, Q>;
@@ -306,12 +331,18 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
     constexpr int d = decltype(dd)::value;
     const int q = tl + TL * d;
     cx<T>* v = buf + d * P;
-    const unsigned toff = (unsigned(q) * unsigned(stride) + unsigned(c)) * CB;
-    static_for<0, live_in<P>()>([&](auto pp) {
-      constexpr int p = decltype(pp)::value;
-      const cx<T>* bp = ubase + (long long)(Q * p) * stride;
-      v[p] = (valid && q + Q * p < nlive) ? ld_at(bp, toff) : zero_c<T>();
-    });
+    const unsigned toff = (unsigned(q) * unsigned(stride) + unsigned(cload)) * CB;
+    if (nlive >= Q * live_in<P>()) {  // every loaded row is live (the zero-padded case)
+      static_for<0, live_in<P>()>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        v[p] = ld_at(ubase + (long long)(Q * p) * stride, toff);
+      });
+    } else {
+      static_for<0, live_in<P>()>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        v[p] = q + Q * p < nlive ? ld_at(ubase + (long long)(Q * p) * stride, toff) : zero_c<T>();
+      });
+    }
     first_dft<P, -1>(v);
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
@@ -419,20 +450,21 @@ constexpr int col_lds_elems() {
 
 // Pass 2: DFT along y, rows y < ny live, all my outputs kept (in place).
 template <typename T, int P, int Q, int C, int NCH>
-__global__ void __launch_bounds__((C * Split<P, Q>::TL))
-k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
+__device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx, unsigned by,
+                                          unsigned bz) {
   using S = Split<P, Q>;
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx0 = blockIdx.x * C;
-  const int z = blockIdx.y, comp = blockIdx.z;
+  const int kx0 = int(bx) * C;
+  const int z = int(by), comp = int(bz);
   const bool valid = kx0 + c < a.kx;
+  const int cload = valid ? c : a.kx - 1 - kx0;  // in-bounds column for the loads
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH>(ubase, a.px, valid, a.ny, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
   if (valid) {
     static_for<0, S::D3>([&](auto dd) {
       constexpr int d = decltype(dd)::value;
@@ -448,26 +480,27 @@ k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
 
 // Pass 4: inverse DFT along y, all my rows in, rows y < ny kept (in place).
 template <typename T, int P, int Q, int C, int NCH>
-__global__ void __launch_bounds__((C * Split<P, Q>::TL))
-k_yinv(cx<T>* __restrict__ W, PassArgs a) {
+__device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx, unsigned by,
+                                          unsigned bz) {
   using S = Split<P, Q>;
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx0 = blockIdx.x * C;
-  const int z = blockIdx.y, comp = blockIdx.z;
+  const int kx0 = int(bx) * C;
+  const int z = int(by), comp = int(bz);
   const bool valid = kx0 + c < a.kx;
+  const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
-    const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(cx<T>));
+    const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(cload)) * unsigned(sizeof(cx<T>));
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
-      w[d][k2] = valid ? ld_at(ubase + (long long)(P * k2) * a.px, toff) : zero_c<T>();
+      w[d][k2] = ld_at(ubase + (long long)(P * k2) * a.px, toff);
     });
   });
   col_inverse<T, P, Q, C, NCH>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
@@ -501,14 +534,13 @@ __device__ __forceinline__ ZconvMap zconv_map(unsigned b, int ntiles, int my, in
 // Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
 // z < nz; in place.  One workgroup per (column tile, ky, component).
 template <typename T, int P, int Q, int C, int NCH>
-__global__ void __launch_bounds__((C * Split<P, Q>::TL))
-k_zconv(cx<T>* __restrict__ W, PassArgs a) {
+__device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using S = Split<P, Q>;
   constexpr int M = S::L;
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int ntiles = (a.kx + C - 1) / C;
-  const ZconvMap mp = zconv_map(blockIdx.x, ntiles, a.my, a.ncomp);
+  const ZconvMap mp = zconv_map(bx, ntiles, a.my, a.ncomp);
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
@@ -518,9 +550,10 @@ k_zconv(cx<T>* __restrict__ W, PassArgs a) {
   const int iy = ky <= a.my - ky ? ky : a.my - ky;
   const T* gbase = static_cast<const T*>(a.ghat) + iy * a.g_plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
+  const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH>(ubase, a.plane, valid, a.nz, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
@@ -529,6 +562,8 @@ k_zconv(cx<T>* __restrict__ W, PassArgs a) {
       const int kz = k1 + P * k2;
       const int iz = kz <= M - kz ? kz : M - kz;
       const unsigned goff = (unsigned(iz) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(T));
+      // (the branch also keeps the scheduler from hoisting these loads,
+      // which would hold 32 more registers through the forward transform)
       const T g = valid ? *reinterpret_cast<const T*>(reinterpret_cast<const char*>(gbase) + goff) : T(0);
       w[d][k2] = scale(w[d][k2], g);
     });
@@ -537,13 +572,101 @@ k_zconv(cx<T>* __restrict__ W, PassArgs a) {
 }
 
 // ============================================================================
-// launchers and the variant table
+// Entry points.  Single-problem kernels take PassArgs by value; grouped
+// kernels run one pass for many problems in one launch: block b belongs to
+// entry bmap[b] of the GroupEntry table, which holds that problem's
+// PassArgs, buffers and first block (a multiple of 8, which keeps the z
+// pass XCD mapping intact).
 // ============================================================================
-static inline int cdiv(long long a, long long b) { return int((a + b - 1) / b); }
+__host__ __device__ inline int cdiv(long long a, long long b) { return int((a + b - 1) / b); }
 
-static inline unsigned zconv_blocks(const PassArgs& a, int C) {
+inline unsigned zconv_blocks(const PassArgs& a, int C) {
   const long long groups = (long long)cdiv(a.kx, C) * (a.my / 2 + 1);
   return unsigned(cdiv(groups, 8) * 8LL * 2 * a.ncomp);
+}
+
+// The problem of this block; *lin = block index inside the problem.  Blocks
+// past the problem's own count (padding to a multiple of 8) return false.
+__device__ __forceinline__ const GroupEntry& group_entry(const GroupArgs& g, unsigned* lin, bool* live) {
+  const GroupEntry& e = g.ents[g.bmap[blockIdx.x]];
+  *lin = blockIdx.x - e.block0;
+  *live = *lin < e.nblocks;
+  return e;
+}
+__device__ __forceinline__ const void* group_in(const GroupArgs& g, const GroupEntry& e) {
+  return e.io_in >= 0 ? g.io[e.io_in] : e.in;
+}
+__device__ __forceinline__ void* group_out(const GroupArgs& g, const GroupEntry& e) {
+  return e.io_out >= 0 ? const_cast<void*>(g.io[e.io_out]) : e.out;
+}
+
+template <typename T, int P, int Q, int RW, int NCH>
+__global__ void __launch_bounds__((RW * Split<P, Q>::TL))
+k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
+  xfwd_body<T, P, Q, RW, NCH>(f, W, a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int P, int Q, int RW, int NCH>
+__global__ void __launch_bounds__((RW * Split<P, Q>::TL)) k_xfwd_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
+  xfwd_body<T, P, Q, RW, NCH>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)), e.a,
+                              lin % gx, lin / gx);
+}
+template <typename T, int P, int Q, int RW, int NCH>
+__global__ void __launch_bounds__((RW * Split<P, Q>::TL))
+k_xinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
+  xinv_body<T, P, Q, RW, NCH>(W, u, a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int P, int Q, int RW, int NCH>
+__global__ void __launch_bounds__((RW * Split<P, Q>::TL)) k_xinv_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
+  xinv_body<T, P, Q, RW, NCH>(static_cast<const cx<T>*>(group_in(g, e)), static_cast<T*>(group_out(g, e)), e.a,
+                              lin % gx, lin / gx);
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
+  yfwd_body<T, P, Q, C, NCH>(W, a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv(e.a.kx, C)), gy = unsigned(e.a.nz);
+  yfwd_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin % gx, (lin / gx) % gy, lin / (gx * gy));
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv(cx<T>* __restrict__ W, PassArgs a) {
+  yinv_body<T, P, Q, C, NCH>(W, a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv(e.a.kx, C)), gy = unsigned(e.a.nz);
+  yinv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin % gx, (lin / gx) % gy, lin / (gx * gy));
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_zconv(cx<T>* __restrict__ W, PassArgs a) {
+  zconv_body<T, P, Q, C, NCH>(W, a, blockIdx.x);
+}
+template <typename T, int P, int Q, int C, int NCH>
+__global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_zconv_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  zconv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 
 template <typename T, int P, int Q, int RW, int NCH>
@@ -575,6 +698,16 @@ void launch_zconv(const PassArgs& a, const void*, void* out, hipStream_t s) {
   hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), dim3(zconv_blocks(a, C)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
+#define UPS_GROUPED_LAUNCHER(kname)                                                                   \
+  template <typename T, int P, int Q, int B, int NCH>                                                  \
+  void launchg_##kname(const GroupArgs& g, unsigned nblocks, hipStream_t s) {                         \
+    hipLaunchKernelGGL((k_##kname##_g<T, P, Q, B, NCH>), dim3(nblocks), dim3(B * Split<P, Q>::TL), 0, s, g); \
+  }
+UPS_GROUPED_LAUNCHER(xfwd)
+UPS_GROUPED_LAUNCHER(xinv)
+UPS_GROUPED_LAUNCHER(yfwd)
+UPS_GROUPED_LAUNCHER(yinv)
+UPS_GROUPED_LAUNCHER(zconv)
 
 template <typename T>
 constexpr int is64() { return sizeof(T) == 8 ? 1 : 0; }
@@ -582,80 +715,32 @@ constexpr int is64() { return sizeof(T) == 8 ? 1 : 0; }
 #define XF_VARIANT(T, P, Q, RW, NCH)                                                           \
   PassVariant{PASS_XFWD, is64<T>(), 2 * P * Q, P, Q, RW, NCH, RW * Split<P, Q>::TL,            \
               int(sizeof(cx<T>)) * (RW / NCH) * xfwd_row_stride<P, Q>(),                        \
-              "xfwd_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xfwd<T, P, Q, RW, NCH>}
+              "xfwd_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xfwd<T, P, Q, RW, NCH>,  \
+              &launchg_xfwd<T, P, Q, RW, NCH>}
 #define XI_VARIANT(T, P, Q, RW, NCH)                                                           \
   PassVariant{PASS_XINV, is64<T>(), 2 * P * Q, P, Q, RW, NCH, RW * Split<P, Q>::TL,            \
               int(sizeof(cx<T>)) * (RW / NCH) * xinv_row_stride<P, Q>(),                        \
-              "xinv_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xinv<T, P, Q, RW, NCH>}
+              "xinv_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH, &launch_xinv<T, P, Q, RW, NCH>,  \
+              &launchg_xinv<T, P, Q, RW, NCH>}
 #define X_VARIANTS(T, P, Q, RW, NCH) XF_VARIANT(T, P, Q, RW, NCH), XI_VARIANT(T, P, Q, RW, NCH)
 
 #define COL_VARIANT(KIND, kname, T, P, Q, C, NCH)                                              \
   PassVariant{KIND, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,                       \
               int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                               \
-              #kname "_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_##kname<T, P, Q, C, NCH>}
+              #kname "_" #T "_" #P "x" #Q "_c" #C "_h" #NCH, &launch_##kname<T, P, Q, C, NCH>, \
+              &launchg_##kname<T, P, Q, C, NCH>}
 #define COL_VARIANTS(T, P, Q, C, NCH)                                                          \
   COL_VARIANT(PASS_YFWD, yfwd, T, P, Q, C, NCH), COL_VARIANT(PASS_ZCONV, zconv, T, P, Q, C, NCH), \
       COL_VARIANT(PASS_YINV, yinv, T, P, Q, C, NCH)
 
-// The first variant listed for a (pass, precision, length) is the default
-// (ordered by measured time on MI355X for the 256^3 and 512^3 grids).
 #define XF(T, P, Q, RW, NCH) XF_VARIANT(T, P, Q, RW, NCH)
 #define XI(T, P, Q, RW, NCH) XI_VARIANT(T, P, Q, RW, NCH)
 #define YF(T, P, Q, C, NCH) COL_VARIANT(PASS_YFWD, yfwd, T, P, Q, C, NCH)
 #define ZC(T, P, Q, C, NCH) COL_VARIANT(PASS_ZCONV, zconv, T, P, Q, C, NCH)
 #define YI(T, P, Q, C, NCH) COL_VARIANT(PASS_YINV, yinv, T, P, Q, C, NCH)
-const std::vector<PassVariant>& pass_variants() {
-  static const std::vector<PassVariant> table = {
-      // ---- float ----
-      X_VARIANTS(float, 4, 4, 16, 1),       // mx = 32
-      X_VARIANTS(float, 4, 8, 16, 1),       // mx = 64
-      X_VARIANTS(float, 8, 8, 16, 2),       // mx = 128
-      X_VARIANTS(float, 8, 16, 16, 2),      // mx = 256
-      X_VARIANTS(float, 16, 16, 16, 2),     // mx = 512
-      XF(float, 16, 32, 16, 2), XF(float, 16, 32, 8, 2), XF(float, 16, 32, 16, 4),   // mx = 1024
-      XI(float, 16, 32, 8, 2), XI(float, 16, 32, 16, 2), XI(float, 16, 32, 16, 4),
-      COL_VARIANTS(float, 4, 8, 16, 1),     // 32
-      COL_VARIANTS(float, 8, 8, 16, 1),     // 64
-      COL_VARIANTS(float, 8, 16, 16, 2),    // 128
-      COL_VARIANTS(float, 16, 16, 16, 2),   // 256
-      COL_VARIANTS(float, 16, 32, 16, 2),   // 512
-      YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
-      ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
-      YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2), YI(float, 32, 32, 16, 4),
-      // ---- double ----
-      X_VARIANTS(double, 4, 4, 8, 1),
-      X_VARIANTS(double, 4, 8, 8, 1),
-      X_VARIANTS(double, 8, 8, 8, 2),
-      X_VARIANTS(double, 8, 16, 8, 2),
-      X_VARIANTS(double, 16, 16, 8, 2),
-      XF(double, 16, 32, 8, 2), XF(double, 16, 32, 8, 4),
-      XI(double, 16, 32, 8, 2), XI(double, 16, 32, 8, 4),
-      COL_VARIANTS(double, 4, 8, 8, 1),
-      COL_VARIANTS(double, 8, 8, 8, 1),
-      COL_VARIANTS(double, 8, 16, 8, 2),
-      COL_VARIANTS(double, 16, 16, 8, 2),
-      YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
-      ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
-      YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
-      YF(double, 32, 32, 8, 2), YF(double, 32, 32, 8, 4),   // 1024
-      ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
-      YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
-  };
-  return table;
-}
 
-int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* gz) {
-  switch (v.kind) {
-    case PASS_XFWD:
-    case PASS_XINV:
-      *gx = cdiv((long long)a.ny * a.nz, v.tile); *gy = a.ncomp; *gz = 1; break;
-    case PASS_YFWD:
-    case PASS_YINV:
-      *gx = cdiv(a.kx, v.tile); *gy = a.nz; *gz = a.ncomp; break;
-    default:
-      *gx = int(zconv_blocks(a, v.tile)); *gy = 1; *gz = 1; break;
-  }
-  return (*gx) * (*gy) * (*gz);
-}
+std::vector<PassVariant> variants_f32_pow2();
+std::vector<PassVariant> variants_f32_mixed();
+std::vector<PassVariant> variants_f64();
 
 }  // namespace ups

@@ -27,6 +27,7 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g);
 void plan_layout(PlanGeom& g);
 double model_bytes(const PlanGeom& g, int pass);
 const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name);
+const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom& g);
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);
 ups_status set_error(ups_status s, const char* msg);

@@ -176,3 +176,90 @@ def solve(f, h, prec=None, pad=None):
     ncomp = 1 if f.dim() == 3 else f.shape[0]
     shape = tuple(f.shape[-3:])
     return Plan(shape, h, prec, ncomp=ncomp, pad=pad).solve(f.contiguous())
+
+
+def _plan_autotune(self, budget_ms=200.0, stream=None):
+    """Time every compiled variant of each pass on this plan (ups_autotune)
+    and keep the fastest; returns the chosen kernel names."""
+    capi.check(capi.lib().ups_autotune(self._h, _stream_handle(stream), float(budget_ms)))
+    return [self.kernel(k) for k in range(5)]
+
+
+Plan.autotune = _plan_autotune
+
+
+class Batch:
+    """Many independent solves (uneven shapes, vector right-hand sides) run
+    as one hipGraph launch (ups_batch_*).
+
+    specs: list of dicts {shape: (nz, ny, nx), h, prec, ncomp, pad}."""
+
+    def __init__(self, specs, setup=True):
+        from .lengths import auto_pad
+        L = capi.lib()
+        self.specs = []
+        probs = (capi.ups_problem * len(specs))()
+        for i, sp in enumerate(specs):
+            shape = tuple(int(v) for v in sp["shape"])
+            prec = sp.get("prec", "f32")
+            ncomp = int(sp.get("ncomp", 1))
+            pad = sp.get("pad") or auto_pad(shape, prec)
+            probs[i] = make_problem(shape, sp["h"], prec, ncomp, pad)
+            self.specs.append(dict(shape=shape, h=float(sp["h"]), prec=prec, ncomp=ncomp, pad=tuple(pad)))
+        handle = C.c_void_p()
+        capi.check(L.ups_batch_create(probs, len(specs), C.byref(handle)))
+        self._h = handle
+        self._probs = probs
+        gb, wb = C.c_size_t(), C.c_size_t()
+        capi.check(L.ups_batch_sizes(self._h, C.byref(gb), C.byref(wb)))
+        self.green_bytes, self.work_bytes = gb.value, wb.value
+        self.green = self.work = None
+        if setup:
+            self.setup()
+
+    def setup(self, device=None, stream=None):
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        self.green = torch.empty(self.green_bytes, dtype=torch.uint8, device=dev)
+        self.work = torch.empty(self.work_bytes, dtype=torch.uint8, device=dev)
+        capi.check(capi.lib().ups_batch_setup(self._h, C.c_void_p(self.green.data_ptr()), self.green_bytes,
+                                              C.c_void_p(self.work.data_ptr()), self.work_bytes,
+                                              _stream_handle(stream)))
+        return self
+
+    def launches(self):
+        return [capi.lib().ups_batch_launches(self._h, k) for k in range(5)]
+
+    def empty_outputs(self):
+        out = []
+        for sp in self.specs:
+            dt = torch.float64 if sp["prec"] == "f64" else torch.float32
+            shape = sp["shape"] if sp["ncomp"] == 1 else (sp["ncomp"],) + sp["shape"]
+            out.append(torch.empty(shape, dtype=dt, device=self.work.device))
+        return out
+
+    def solve(self, fs, us=None, stream=None):
+        n = len(self.specs)
+        if len(fs) != n:
+            raise ValueError("expected %d source arrays" % n)
+        us = self.empty_outputs() if us is None else us
+        for f, u, sp in zip(fs, us, self.specs):
+            dt = torch.float64 if sp["prec"] == "f64" else torch.float32
+            shape = sp["shape"] if sp["ncomp"] == 1 else (sp["ncomp"],) + sp["shape"]
+            for t in (f, u):
+                if not t.is_cuda or t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+                    raise ValueError("batch array must be a contiguous %s tensor of shape %s" % (dt, shape))
+        fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+        up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+        capi.check(capi.lib().ups_batch_solve(self._h, fp, up, _stream_handle(stream)))
+        return us
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().ups_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
