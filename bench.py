@@ -106,6 +106,92 @@ def cpu_baseline(n_sample=256):
                       "G_hat precomputed; %.2f s" % (n_sample, workers, dt)}
 
 
+def batch_leg(reps=10):
+    """The uneven batch (48 solves of 32..192 points per axis + a 3-component
+    128^3 curl source, FP32): one graph launch vs a loop of per-problem
+    plans running the same kernels eagerly."""
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.solver import Batch, Plan
+    cfg = workloads.config_c4()
+    specs = [dict(shape=p["shape"], h=p["h"], prec="f32") for p in cfg["scalar"]]
+    specs.append(dict(shape=cfg["vector"]["shape"], h=cfg["vector"]["h"], prec="f32", ncomp=3))
+    fs = [torch.from_numpy(p["f"].astype(np.float32)).cuda() for p in cfg["scalar"]]
+    fs.append(torch.from_numpy(cfg["vector"]["f"].astype(np.float32)).cuda())
+    t0 = time.perf_counter()
+    b = Batch(specs)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    us = b.empty_outputs()
+    plans = [Plan(sp["shape"], sp["h"], "f32", ncomp=sp["ncomp"], pad=sp["pad"]) for sp in b.specs]
+    pts = sum(int(np.prod(sp["shape"])) * sp["ncomp"] for sp in b.specs)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    graph_ms = timed(lambda: b.solve(fs, us))
+    loop_ms = timed(lambda: [p.solve(f, out=u) for p, f, u in zip(plans, fs, us)])
+    return {"problems": len(specs), "points": pts, "graph_ms": graph_ms, "loop_ms": loop_ms,
+            "graph_pts_per_s": pts / (graph_ms * 1e-3), "batched_speedup_over_loop": loop_ms / graph_ms,
+            "launches_per_pass": b.launches(), "setup_ms": setup_ms}
+
+
+def grad_leg(n=256, reps=5):
+    """Differentiable workload: 256^3 FP32 forward solve + loss + backward
+    through the hand-written adjoint (torch.autograd)."""
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.autograd import poisson_solve
+    from paper_2512_08555_amd.solver import Plan
+    h = 1.0 / n
+    f = torch.from_numpy(workloads.config_blobs_noise(n, 5).astype(np.float32)).cuda()
+    w = torch.from_numpy(workloads.weight_field(n, h, seed=55).astype(np.float32)).cuda()
+    plan = Plan((n, n, n), h, "f32")
+    inv = 1.0 / (2.0 * h)
+
+    def step():
+        fr = f.detach().requires_grad_(True)
+        u = poisson_solve(fr, plan)
+        dx = (u[1:-1, 1:-1, 2:] - u[1:-1, 1:-1, :-2]) * inv
+        dy = (u[1:-1, 2:, 1:-1] - u[1:-1, :-2, 1:-1]) * inv
+        dz = (u[2:, 1:-1, 1:-1] - u[:-2, 1:-1, 1:-1]) * inv
+        L = h ** 3 * (w[1:-1, 1:-1, 1:-1] * (dx * dx + dy * dy + dz * dz)).sum()
+        L.backward()
+        return fr.grad
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"n": n, "fwd_bwd_ms": ms, "solves_per_step": 2}
+
+
+def calibrate_copy(nbytes=2 << 30, reps=3):
+    """A plain copy of known size (reads and writes nbytes each) whose
+    FETCH_SIZE / WRITE_SIZE readings calibrate the HBM counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.add(a, 0.0, out=b)
+    torch.cuda.synchronize()
+    return {"bytes": nbytes, "reps": reps, "grid_elements": a.numel()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +200,10 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 2 GiB copy kernel (for counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -171,6 +261,15 @@ def main():
             "f64_pass_ms": dict(zip(PASS_NAMES, [round(float(x), 4) for x in pp64])),
         }
         del p64
+
+    if not args.no_batch:
+        extra["batch"] = batch_leg()
+        torch.cuda.empty_cache()
+    if not args.no_grad:
+        extra["grad_256"] = grad_leg()
+        torch.cuda.empty_cache()
+    if args.calibrate_copy:
+        extra["copy_calibration"] = calibrate_copy()
 
     cpu = None
     if not args.no_cpu:

@@ -1,6 +1,6 @@
 // Registry of the compiled pass kernels (instantiated in passes_f32.hip,
 // passes_f32m.hip and passes_f64.hip).
-#include "passes.hpp"
+#include "passes_impl.hpp"
 
 namespace ups {
 
@@ -22,18 +22,23 @@ const std::vector<PassVariant>& pass_variants() {
 
 static inline int cdiv_ll(long long a, long long b) { return int((a + b - 1) / b); }
 
+// Blocks one launch of variant v needs for problem a (as the launchers in
+// passes_impl.hpp compute them).
 int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* gz) {
+  const int per_line = 128 / (v.is_f64 ? 16 : 8);
+  const int H = per_line > v.tile ? per_line / v.tile : 1;
+  const int ntiles = cdiv_ll(a.kx, v.tile);
+  *gy = 1;
+  *gz = 1;
   switch (v.kind) {
     case PASS_XFWD:
     case PASS_XINV:
-      *gx = cdiv_ll((long long)a.ny * a.nz, v.tile); *gy = a.ncomp; *gz = 1; break;
+      *gx = cdiv_ll((long long)a.ny * a.nz, v.tile); *gy = a.ncomp; break;
     case PASS_YFWD:
     case PASS_YINV:
-      *gx = cdiv_ll(a.kx, v.tile); *gy = a.nz; *gz = a.ncomp; break;
-    default: {
-      const long long groups = (long long)cdiv_ll(a.kx, v.tile) * (a.my / 2 + 1);
-      *gx = int(cdiv_ll(groups, 8) * 8LL * 2 * a.ncomp); *gy = 1; *gz = 1; break;
-    }
+      *gx = int(ymap_blocks(ntiles, a.nz, a.ncomp, H)); break;
+    default:
+      *gx = int(zmap_blocks(ntiles, a.my, a.ncomp, H)); break;
   }
   return (*gx) * (*gy) * (*gz);
 }

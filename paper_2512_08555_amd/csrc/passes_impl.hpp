@@ -448,17 +448,80 @@ constexpr int col_lds_elems() {
   return a > b ? a : b;
 }
 
+// Block orders of the column passes.  Consecutive linear block ids go
+// round-robin to the eight XCDs, each with its own L2.  A tile of C columns
+// may cover only part of a 128-byte line (C = 8 float columns = 64 bytes), so
+// the H = (128 B / element) / C tiles of one line are made "slots" of one
+// group, with linear ids 8 apart: same XCD, close in time, so the line is
+// fetched from HBM once.  The z pass adds to the group every workgroup that
+// reads the same G_hat octant line (ky = iy and my - iy, every component).
+template <typename T, int C>
+constexpr int tile_slots() {
+  constexpr int per_line = 128 / int(sizeof(cx<T>));
+  return per_line > C ? per_line / C : 1;
+}
+
+struct ColMap {
+  int tile, line, comp;   // line = z (y passes) or ky (z pass)
+  bool active;
+};
+
+// y passes: groups (tile group, z, comp), slots = tile within the group
+__device__ __forceinline__ ColMap ymap(unsigned b, int ntiles, int nz, int ncomp, int H) {
+  const unsigned x = b % 8u, rest = b / 8u;
+  const int slot = int(rest % unsigned(H));
+  const unsigned g = (rest / unsigned(H)) * 8u + x;
+  const unsigned ntg = unsigned((ntiles + H - 1) / H);
+  ColMap m;
+  m.active = g < ntg * unsigned(nz) * unsigned(ncomp);
+  const unsigned tg = g % ntg, r = g / ntg;
+  m.line = int(r % unsigned(nz));
+  m.comp = int(r / unsigned(nz));
+  m.tile = int(tg) * H + slot;
+  if (m.tile >= ntiles) m.active = false;
+  return m;
+}
+__host__ __device__ inline unsigned ymap_blocks(int ntiles, int nz, int ncomp, int H) {
+  const long long groups = (long long)((ntiles + H - 1) / H) * nz * ncomp;
+  return unsigned((groups + 7) / 8 * 8 * H);
+}
+
+// z pass: groups (tile group, iy), slots = (tile in group, side, comp)
+__device__ __forceinline__ ColMap zmap(unsigned b, int ntiles, int my, int ncomp, int H) {
+  const int slots = H * 2 * ncomp;
+  const unsigned x = b % 8u, rest = b / 8u;
+  const int slot = int(rest % unsigned(slots));
+  const unsigned g = (rest / unsigned(slots)) * 8u + x;
+  const int oy = my / 2 + 1;
+  const unsigned ntg = unsigned((ntiles + H - 1) / H);
+  ColMap m;
+  m.active = g < ntg * unsigned(oy);
+  const int iy = int(g / ntg);
+  const int half = slot % H, side = (slot / H) & 1;
+  m.comp = slot / (2 * H);
+  m.tile = int(g % ntg) * H + half;
+  m.line = side ? my - iy : iy;
+  if (m.tile >= ntiles) m.active = false;
+  if (side && (iy == 0 || 2 * iy == my)) m.active = false;  // self-mirrored line
+  return m;
+}
+__host__ __device__ inline unsigned zmap_blocks(int ntiles, int my, int ncomp, int H) {
+  const long long groups = (long long)((ntiles + H - 1) / H) * (my / 2 + 1);
+  return unsigned((groups + 7) / 8 * 8 * H * 2 * ncomp);
+}
+
 // Pass 2: DFT along y, rows y < ny live, all my outputs kept (in place).
 template <typename T, int P, int Q, int C, int NCH>
-__device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx, unsigned by,
-                                          unsigned bz) {
+__device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned blin) {
   using S = Split<P, Q>;
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx0 = int(bx) * C;
-  const int z = int(by), comp = int(bz);
+  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, tile_slots<T, C>());
+  if (!mp.active) return;  // uniform over the workgroup, before any barrier
+  const int kx0 = mp.tile * C;
+  const int z = mp.line, comp = mp.comp;
   const bool valid = kx0 + c < a.kx;
   const int cload = valid ? c : a.kx - 1 - kx0;  // in-bounds column for the loads
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
@@ -480,15 +543,16 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
 
 // Pass 4: inverse DFT along y, all my rows in, rows y < ny kept (in place).
 template <typename T, int P, int Q, int C, int NCH>
-__device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx, unsigned by,
-                                          unsigned bz) {
+__device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned blin) {
   using S = Split<P, Q>;
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const int kx0 = int(bx) * C;
-  const int z = int(by), comp = int(bz);
+  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, tile_slots<T, C>());
+  if (!mp.active) return;  // uniform over the workgroup, before any barrier
+  const int kx0 = mp.tile * C;
+  const int z = mp.line, comp = mp.comp;
   const bool valid = kx0 + c < a.kx;
   const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
@@ -506,31 +570,6 @@ __device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs&
   col_inverse<T, P, Q, C, NCH>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
 }
 
-// Pass 3 block order.  The workgroups that read the same G_hat octant line
-// (tile, iy) -- ky = iy and ky = my - iy, every component -- get linear
-// block ids 8 apart: consecutive blocks go round-robin to the eight XCDs,
-// so these land on one XCD, close in time, and share its L2.
-struct ZconvMap {
-  int tile, ky, comp;
-  bool active;
-};
-__device__ __forceinline__ ZconvMap zconv_map(unsigned b, int ntiles, int my, int ncomp) {
-  const int slots = 2 * ncomp;
-  const unsigned x = b % 8u, rest = b / 8u;
-  const int slot = int(rest % unsigned(slots));
-  const unsigned g = (rest / unsigned(slots)) * 8u + x;
-  const int oy = my / 2 + 1;
-  ZconvMap m;
-  m.active = g < unsigned(ntiles) * unsigned(oy);
-  const int iy = int(g / unsigned(ntiles));
-  m.tile = int(g % unsigned(ntiles));
-  const int side = slot & 1;
-  m.comp = slot >> 1;
-  m.ky = side ? my - iy : iy;
-  if (side && (iy == 0 || 2 * iy == my)) m.active = false;  // self-mirrored line
-  return m;
-}
-
 // Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
 // z < nz; in place.  One workgroup per (column tile, ky, component).
 template <typename T, int P, int Q, int C, int NCH>
@@ -540,12 +579,12 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int ntiles = (a.kx + C - 1) / C;
-  const ZconvMap mp = zconv_map(bx, ntiles, a.my, a.ncomp);
+  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, tile_slots<T, C>());
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
   const int kx0 = mp.tile * C;
-  const int ky = mp.ky;
+  const int ky = mp.line;
   const bool valid = kx0 + c < a.kx;
   const int iy = ky <= a.my - ky ? ky : a.my - ky;
   const T* gbase = static_cast<const T*>(a.ghat) + iy * a.g_plane + kx0;
@@ -580,9 +619,13 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
 // ============================================================================
 __host__ __device__ inline int cdiv(long long a, long long b) { return int((a + b - 1) / b); }
 
-inline unsigned zconv_blocks(const PassArgs& a, int C) {
-  const long long groups = (long long)cdiv(a.kx, C) * (a.my / 2 + 1);
-  return unsigned(cdiv(groups, 8) * 8LL * 2 * a.ncomp);
+template <typename T, int C>
+inline unsigned zconv_blocks(const PassArgs& a) {
+  return zmap_blocks(cdiv(a.kx, C), a.my, a.ncomp, tile_slots<T, C>());
+}
+template <typename T, int C>
+inline unsigned ypass_blocks(const PassArgs& a) {
+  return ymap_blocks(cdiv(a.kx, C), a.nz, a.ncomp, tile_slots<T, C>());
 }
 
 // The problem of this block; *lin = block index inside the problem.  Blocks
@@ -632,7 +675,7 @@ __global__ void __launch_bounds__((RW * Split<P, Q>::TL)) k_xinv_g(GroupArgs g) 
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
-  yfwd_body<T, P, Q, C, NCH>(W, a, blockIdx.x, blockIdx.y, blockIdx.z);
+  yfwd_body<T, P, Q, C, NCH>(W, a, blockIdx.x);
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd_g(GroupArgs g) {
@@ -640,12 +683,11 @@ __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd_g(GroupArgs g) {
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  const unsigned gx = unsigned(cdiv(e.a.kx, C)), gy = unsigned(e.a.nz);
-  yfwd_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin % gx, (lin / gx) % gy, lin / (gx * gy));
+  yfwd_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv(cx<T>* __restrict__ W, PassArgs a) {
-  yinv_body<T, P, Q, C, NCH>(W, a, blockIdx.x, blockIdx.y, blockIdx.z);
+  yinv_body<T, P, Q, C, NCH>(W, a, blockIdx.x);
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv_g(GroupArgs g) {
@@ -653,8 +695,7 @@ __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv_g(GroupArgs g) {
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  const unsigned gx = unsigned(cdiv(e.a.kx, C)), gy = unsigned(e.a.nz);
-  yinv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin % gx, (lin / gx) % gy, lin / (gx * gy));
+  yinv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_zconv(cx<T>* __restrict__ W, PassArgs a) {
@@ -683,19 +724,17 @@ void launch_xinv(const PassArgs& a, const void* in, void* out, hipStream_t s) {
 }
 template <typename T, int P, int Q, int C, int NCH>
 void launch_yfwd(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  dim3 grid(cdiv(a.kx, C), a.nz, a.ncomp);
-  hipLaunchKernelGGL((k_yfwd<T, P, Q, C, NCH>), grid, dim3(C * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_yfwd<T, P, Q, C, NCH>), dim3(ypass_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
 template <typename T, int P, int Q, int C, int NCH>
 void launch_yinv(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  dim3 grid(cdiv(a.kx, C), a.nz, a.ncomp);
-  hipLaunchKernelGGL((k_yinv<T, P, Q, C, NCH>), grid, dim3(C * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_yinv<T, P, Q, C, NCH>), dim3(ypass_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
 template <typename T, int P, int Q, int C, int NCH>
 void launch_zconv(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), dim3(zconv_blocks(a, C)), dim3(C * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), dim3(zconv_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
 #define UPS_GROUPED_LAUNCHER(kname)                                                                   \
