@@ -14,7 +14,7 @@
  *
  * i.e. the exact decaying solution of the discrete problem for a source that
  * vanishes outside the box.  It is evaluated in spectral space, u_hat =
- * G_hat f_hat (Sec. 2.2), on a grid zero-padded to M_i >= 2 N_i - 2 points per
+ * G_hat f_hat (Sec. 2.2), on a grid zero-padded to M_i >= 2 N_i points per
  * axis (default 2 N_i), with the real, even spectrum G_hat of the evenly
  * periodised G1 computed once by ups_plan_setup.
  *
@@ -84,7 +84,7 @@ typedef struct {
   int ncomp;       /* components solved together (1..8), e.g. 3 for a
                       vector right-hand side; they share G_hat            */
   int pad[3];      /* padded FFT length per axis; 0 = 2 n. Must be even,
-                      >= 2 n - 2 and a supported length (ups_supported_length) */
+                      >= 2 n and a supported length (ups_supported_length) */
 } ups_problem;
 
 typedef struct ups_plan_s* ups_plan_t;
@@ -105,9 +105,9 @@ int ups_supported_length(int len, int prec);
 void ups_problem_init(ups_problem* p);
 
 /* Validate the problem and build a host-side plan (no device work).
- * Errors: INVALID_ARG (null, n < 2, h <= 0, ncomp out of range, pad too small
- * or odd), UNSUPPORTED (non-UNB side, Mehrstellen kernel, anisotropic h,
- * padded length without a compiled kernel). */
+ * Errors: INVALID_ARG (null, n < 2, h <= 0, ncomp out of range, pad below
+ * 2 n or odd), UNSUPPORTED (non-UNB side, Mehrstellen kernel, anisotropic h,
+ * n > 4096, padded length without a compiled kernel). */
 ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out);
 
 /* Bytes the caller must provide: green = G_hat octant plus twiddle tables,

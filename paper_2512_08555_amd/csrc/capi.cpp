@@ -80,10 +80,12 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   const bool f64 = p->prec == UPS_F64;
   int M[3];
   for (int i = 0; i < 3; ++i) {
+    // Any even M >= 2n - 2 makes the circular convolution exact, but the
+    // kernels prune on inputs n >= M/2 being zero and outputs n >= M/2
+    // being dropped, which needs M >= 2n.
     M[i] = p->pad[i] ? p->pad[i] : 2 * p->n[i];
-    if (M[i] % 2 || M[i] < 2 * p->n[i] - 2)
-      return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: must be even and >= 2 n - 2 = %d", i, M[i],
-                  2 * p->n[i] - 2);
+    if (M[i] % 2 || M[i] < 2 * p->n[i])
+      return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: must be even and >= 2 n = %d", i, M[i], 2 * p->n[i]);
   }
   for (int i = 0; i < 3; ++i) {
     if (!length_supported(M[i], f64))

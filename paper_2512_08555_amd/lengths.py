@@ -7,7 +7,8 @@ def supported_length(m, prec="f64"):
 
 
 def auto_pad(shape, prec="f64"):
-    """Smallest supported even length >= 2 n per axis for a (nz, ny, nx) grid."""
+    """Smallest supported padded length >= 2 n per axis for a (nz, ny, nx)
+    grid (the kernels need M >= 2 n; see include/ups.h)."""
     out = []
     for n in shape:
         m = 2 * int(n)

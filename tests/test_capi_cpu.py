@@ -83,6 +83,10 @@ def test_validation_errors():
 
     p = make_problem((20, 20, 20), 1 / 20, pad=(36, 40, 40))   # 36 < 2*20-2
     assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
+    # 2n - 2 is exact for the convolution but the pruned kernels need 2n
+    p = make_problem((33, 20, 20), 1 / 33, pad=(64, 64, 64))
+    s, _, msg = _create(p)
+    assert s == capi.UPS_ERR_INVALID_ARG and ">= 2 n" in msg
     p = make_problem((20, 20, 20), 1 / 20, pad=(40, 40, 41))   # odd
     assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
     p = make_problem((20, 20, 20), 1 / 20)                      # 40: no kernel
@@ -144,4 +148,43 @@ def test_calls_before_setup_and_without_device_fail_cleanly():
         s = L.ups_plan_setup(h, C.c_void_p(256), g.value, C.c_void_p(1 << 20), w.value, None)
         assert s == capi.UPS_ERR_DEVICE
         assert "device" in L.ups_last_error().decode()
+    L.ups_plan_destroy(h)
+
+
+def test_batch_validation_without_device():
+    L = _lib_or_skip()
+    good = make_problem((20, 30, 40), 0.05, prec="f32", pad=(64, 64, 80))
+    bad = make_problem((20, 30, 1), 0.05)
+    arr = (capi.ups_problem * 2)(good, bad)
+    h = C.c_void_p()
+    assert L.ups_batch_create(arr, 2, C.byref(h)) == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_batch_create(arr, 0, C.byref(h)) == capi.UPS_ERR_INVALID_ARG
+    many = (capi.ups_problem * 201)(*([good] * 201))
+    assert L.ups_batch_create(many, 201, C.byref(h)) == capi.UPS_ERR_UNSUPPORTED
+    arr = (capi.ups_problem * 3)(good, make_problem((16, 16, 16), 1 / 16, prec="f64"),
+                                  make_problem((24, 24, 24), 1 / 24, prec="f32", ncomp=3, pad=(64, 64, 64)))
+    assert L.ups_batch_create(arr, 3, C.byref(h)) == capi.UPS_OK
+    g, w = C.c_size_t(), C.c_size_t()
+    assert L.ups_batch_sizes(h, C.byref(g), C.byref(w)) == capi.UPS_OK
+    assert g.value > 0 and w.value > 0
+    assert all(L.ups_batch_launches(h, k) >= 1 for k in range(5))
+    assert L.ups_batch_launches(h, 5) == 0
+    fp = (C.c_void_p * 3)(4096, 8192, 12288)
+    assert L.ups_batch_solve(h, fp, fp, None) == capi.UPS_ERR_STATE
+    assert L.ups_batch_setup(h, C.c_void_p(256), g.value - 1, C.c_void_p(512), w.value,
+                             None) == capi.UPS_ERR_WORKSPACE
+    import torch
+    if not torch.cuda.is_available():
+        assert L.ups_batch_setup(h, C.c_void_p(256), g.value, C.c_void_p(512), w.value,
+                                 None) == capi.UPS_ERR_DEVICE
+    assert L.ups_batch_destroy(h) == capi.UPS_OK
+
+
+def test_autotune_requires_setup():
+    L = _lib_or_skip()
+    p = make_problem((32, 32, 32), 1 / 32)
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    assert L.ups_autotune(h, None, 10.0) == capi.UPS_ERR_STATE
+    assert L.ups_autotune(None, None, 10.0) == capi.UPS_ERR_INVALID_ARG
     L.ups_plan_destroy(h)

@@ -1,0 +1,106 @@
+"""Parity at the benchmark sizes and edge cases of the solve."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2512_08555_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print("[case]", msg, flush=True)
+
+
+def _rel_inf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _plan(shape, h, prec, pad=None, ncomp=1):
+    from paper_2512_08555_amd.lengths import auto_pad
+    from paper_2512_08555_amd.solver import Plan
+    return Plan(shape, h, prec, ncomp=ncomp, pad=pad or auto_pad(shape, prec))
+
+
+def test_c2_256_f64_full_field():
+    cfg = workloads.config_c2()
+    _announce("c2 256^3 f64 full field")
+    f, h = cfg["f"], cfg["h"]
+    plan = _plan(cfg["shape"], h, "f64")
+    assert plan.padded == (512, 512, 512)
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    t0 = time.time()
+    ref = oracle.solve(f, h)
+    print("oracle 256^3: %.1f s" % (time.time() - t0), flush=True)
+    err = _rel_inf(u, ref)
+    print("c2 rel Linf %.3e" % err, flush=True)
+    assert err < 1e-12
+
+
+def test_c3_512_f32_full_field_and_samples():
+    cfg = workloads.config_c3()
+    _announce("c3 512^3 f32 full field vs FP64 oracle")
+    f32 = cfg["f"].astype(np.float32)
+    h = cfg["h"]
+    plan = _plan(cfg["shape"], h, "f32")
+    assert plan.padded == (1024, 1024, 1024)
+    u = plan.solve(torch.from_numpy(f32).cuda()).double().cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    fd = f32.astype(np.float64)
+    t0 = time.time()
+    ref = oracle.solve(fd, h)
+    print("oracle 512^3: %.1f s" % (time.time() - t0), flush=True)
+    linf = _rel_inf(u, ref)
+    l2 = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    print("c3 f32 rel Linf %.3e rel L2 %.3e" % (linf, l2), flush=True)
+    assert linf < 2e-6 and l2 < 1e-6
+    # sampled outputs against the defining lattice sum, evaluated one by one
+    # on a 64^3 corner sub-problem (same kernel, same precision path)
+    sub = fd[:64, :64, :64].copy()
+    ps = _plan(sub.shape, h, "f32")
+    us = ps.solve(torch.from_numpy(sub.astype(np.float32)).cuda()).double().cpu().numpy()
+    G1 = oracle.lgf_table(64, 64, 64)
+    rng = np.random.default_rng(0)
+    i = np.arange(64)
+    for _ in range(6):
+        p = tuple(int(v) for v in rng.integers(0, 64, 3))
+        ker = G1[np.ix_(np.abs(i - p[0]), np.abs(i - p[1]), np.abs(i - p[2]))]
+        val = h * h * float((ker * sub).sum())
+        assert abs(us[p] - val) < 2e-6 * np.abs(us).max()
+
+
+@pytest.mark.parametrize("shape,prec", [((2, 2, 2), "f64"), ((3, 4, 5), "f32"), ((7, 3, 2), "f64"),
+                                        ((3, 4, 511), "f32"), ((2, 511, 3), "f64")])
+def test_edge_shapes(shape, prec):
+    _announce("edge %s %s" % (shape, prec))
+    rng = np.random.default_rng(sum(shape))
+    f = rng.standard_normal(shape)
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    h = 0.1
+    plan = _plan(shape, h, prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    ref = oracle.solve(f, h, M=plan.padded)
+    assert _rel_inf(u, ref) < (1e-12 if prec == "f64" else 3e-6)
+
+
+def test_zero_input_and_delta_source():
+    _announce("zero and delta 20^3 f64")
+    n = 20
+    h = 0.3
+    plan = _plan((n, n, n), h, "f64")
+    z = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    assert torch.count_nonzero(plan.solve(z)).item() == 0
+    f = np.zeros((n, n, n))
+    c = (0, 19, 7)   # a corner-adjacent delta: offsets up to 19 per axis
+    f[c] = 1.0
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    i = np.arange(n)
+    G1 = oracle.lgf_table(n, n, n)
+    ref = h * h * G1[np.ix_(np.abs(i - c[0]), np.abs(i - c[1]), np.abs(i - c[2]))]
+    assert np.abs(u - ref).max() < 1e-14
