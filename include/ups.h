@@ -142,10 +142,29 @@ ups_status ups_solve_adjoint(ups_plan_t plan, const void* grad_u, void* grad_f, 
  * y-forward, z-convolution, y-inverse, x-inverse), or NULL. */
 const char* ups_plan_kernel(ups_plan_t plan, int pass);
 
+/* Names of the compiled kernel variants of pass 0..4 for padded length
+ * `len` in precision `prec` (ups_prec): writes up to `cap` of them to
+ * `names` (static strings owned by the library; `names` may be NULL when cap
+ * is 0) and returns how many exist (0 for bad arguments).  The first one is
+ * the default a new plan uses when no tuning result is cached. */
+int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap);
+
 /* Select the compiled variant `name` for pass 0..4 (names as returned by
  * ups_plan_kernel; used by tuning).  INVALID_ARG if no such variant exists
  * for the pass, precision and padded length. */
 ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
+
+/* Schedule of the three column passes (y-forward, z-convolution,
+ * y-inverse), which treat every x frequency kx independently.  With
+ * `columns` = w > 0 they run slab by slab over kx in [0, w), [w, 2w), ...
+ * (the last slab also takes the remainder), so that each slab's padded
+ * spectrum is still in the device's last-level cache when the next pass
+ * reads it; 0 runs each pass once over all columns.  The result does not
+ * depend on the schedule (bitwise).  INVALID_ARG unless w is 0 or a positive
+ * multiple of 16.  ups_plan_create picks a default from the problem size;
+ * ups_plan_slab returns the current width (0 = one slab), or -1 for NULL. */
+ups_status ups_plan_set_slab(ups_plan_t plan, int columns);
+int ups_plan_slab(ups_plan_t plan);
 
 /* Enqueue one pass of the solve on the bound work buffer W, for testing and
  * per-kernel timing: pass 0 reads the real array `in` and writes W; passes
@@ -153,8 +172,8 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
  * array `out`.  W holds complex values [c][z][y][kx] with kx fastest, row
  * pitch `pitch`, plane stride `plane` and component stride `comp_stride`
  * (complex elements); G_hat (real, plan precision) sits at byte
- * `ghat_offset` of the green buffer as [iy][iz][kx], iy stride `ghat_plane`
- * and iz stride `pitch`. */
+ * `ghat_offset` of the green buffer as [iy][kx][iz] (iz fastest), iy stride
+ * `ghat_plane` and kx stride `ghat_plane` / (mx/2 + 1). */
 ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, void* stream);
 ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long long* comp_stride,
                            size_t* ghat_offset, long long* ghat_plane);

@@ -54,9 +54,12 @@ SIGNATURES = {
     "ups_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ups_plan_kernel": (C.c_char_p, [C.c_void_p, C.c_int]),
     "ups_plan_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
+    "ups_kernel_variants": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_char_p), C.c_int]),
     "ups_run_pass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ups_plan_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_longlong), C.POINTER(C.c_size_t), C.POINTER(C.c_longlong)]),
+    "ups_plan_set_slab": (C.c_int, [C.c_void_p, C.c_int]),
+    "ups_plan_slab": (C.c_int, [C.c_void_p]),
     "ups_plan_model_bytes": (C.c_double, [C.c_void_p, C.c_int]),
     "ups_plan_destroy": (C.c_int, [C.c_void_p]),
     "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),

@@ -122,9 +122,13 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
     for (const PassVariant* v : cands) {
       if (spent > budget_ms && v != plan->var[k]) continue;
       const int reps = 5;
-      v->launch(plan->args, work, work, st);  // warm-up
+      auto run = [&]() {
+        if (k == 2) enqueue_zpass(g, v, plan->args, work, st);
+        else v->launch(plan->args, work, work, st);
+      };
+      run();  // warm-up
       err = hipEventRecord(e0, st);
-      for (int r = 0; r < reps && err == hipSuccess; ++r) v->launch(plan->args, work, work, st);
+      for (int r = 0; r < reps && err == hipSuccess; ++r) run();
       if (err == hipSuccess) err = hipEventRecord(e1, st);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;

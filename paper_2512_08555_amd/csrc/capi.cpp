@@ -2,6 +2,7 @@
 // entry points.  See include/ups.h for the contract of every call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -104,6 +105,7 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   g->oy = g->my / 2 + 1;
   g->oz = g->mz / 2 + 1;
   g->px = int(align_up(size_t(g->kx), 16));
+  g->gz = int(align_up(size_t(g->oz), 16));
   g->ncomp = p->ncomp;
   g->h = p->h[0];
   return UPS_OK;
@@ -116,17 +118,17 @@ void plan_layout(PlanGeom& g) {
   g.solve_work = align_up(ce * (size_t)g.comp_w * g.ncomp, 256);
   const GreenScratch gs = green_scratch_layout(g.oz, g.oy, g.kx);
   const int mmax = std::max(g.mx, std::max(g.my, g.mz));
-  const size_t setup = std::max(gs.bytes, align_up(sizeof(double) * 2 * (size_t)mmax, 256));
+  const size_t setup = std::max(gs.bytes, align_up(sizeof(double) * 2 * twiddle_entries(mmax), 256));
   g.work_bytes = std::max(g.solve_work, setup);
   size_t off = 0;
   g.off_ghat = off;
-  off = align_up(off + g.elem * (size_t)g.oy * g.oz * g.px, 256);
+  off = align_up(off + g.elem * (size_t)g.oy * g.kx * g.gz, 256);
   g.off_twx = off;
-  off = align_up(off + ce * g.mx, 256);
+  off = align_up(off + ce * twiddle_entries(g.mx), 256);
   g.off_twy = off;
-  off = align_up(off + ce * g.my, 256);
+  off = align_up(off + ce * twiddle_entries(g.my), 256);
   g.off_twz = off;
-  off = align_up(off + ce * g.mz, 256);
+  off = align_up(off + ce * twiddle_entries(g.mz), 256);
   g.green_bytes = off;
 }
 
@@ -180,7 +182,8 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
   a.plane = g.plane;
   a.comp_w = g.comp_w;
   a.comp_f = (long long)g.nx * g.ny * g.nz;
-  a.g_plane = (long long)g.oz * g.px;
+  a.gz = g.gz;
+  a.g_plane = (long long)g.kx * g.gz;
   a.ncomp = g.ncomp;
   const char* gb = static_cast<const char*>(green);
   a.ghat = gb + g.off_ghat;
@@ -190,12 +193,77 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
   return a;
 }
 
-ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a,
+// Column slabs.  The y-forward, z and y-inverse passes act on each kx
+// column independently, so they can run slab by slab: y-forward, z, y-inverse
+// on columns [k0, k0 + w), then the next slab.  A slab's padded spectrum
+// (w * my * nz complex values per component) then stays in the device's
+// last-level cache from the pass that writes it to the pass that reads it.
+// Slab starts are multiples of 16 columns (128-byte lines of float complex
+// values); the last slab also takes the remainder.
+// Measured on MI355X at 512^3: slabs do not pay (the column passes are not
+// limited by HBM traffic), so plans start with one slab.
+int default_slab(const PlanGeom&) { return 0; }
+
+int slab_count(const PlanGeom& g, int slab) {
+  if (slab <= 0 || slab >= g.kx) return 1;
+  return std::max(1, g.kx / slab);
+}
+
+PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* work, void** wslab) {
+  const int ns = slab_count(g, slab);
+  if (ns == 1) {
+    *wslab = work;
+    return a;
+  }
+  const int k0 = s * slab;
+  const int k1 = s == ns - 1 ? g.kx : k0 + slab;
+  PassArgs b = a;
+  b.kx = k1 - k0;
+  b.ghat = static_cast<const char*>(a.ghat) + size_t(k0) * g.gz * g.elem;
+  *wslab = static_cast<char*>(work) + size_t(k0) * 2 * g.elem;
+  return b;
+}
+
+// The z pass over columns [k0, k0 + w) of W (and of G_hat).
+static PassArgs column_range(const PlanGeom& g, const PassArgs& a, int k0, int w, void* ws, void** out) {
+  PassArgs b = a;
+  b.kx = w;
+  b.ghat = static_cast<const char*>(a.ghat) + size_t(k0) * g.gz * g.elem;
+  *out = static_cast<char*>(ws) + size_t(k0) * 2 * g.elem;
+  return b;
+}
+
+// Wave-per-line z kernels run best when every XCD keeps the same columns
+// for all lines and all XCDs get equal shares: the launch covers a multiple
+// of 8 x (columns per 128-byte line) columns, and the few columns left over
+// go to a one-column-wide variant.
+void enqueue_zpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st) {
+  const int align = 8 * (128 / int(2 * g.elem));
+  const PassVariant* nv = v->nch == 0 ? narrow_variant(*v) : nullptr;
+  const int kmain = a.kx / align * align;
+  if (!nv || kmain == 0 || kmain == a.kx) {
+    v->launch(a, ws, ws, st);
+    return;
+  }
+  void* wm = nullptr;
+  void* wr = nullptr;
+  const PassArgs am = column_range(g, a, 0, kmain, ws, &wm);
+  const PassArgs ar = column_range(g, a, kmain, a.kx - kmain, ws, &wr);
+  v->launch(am, wm, wm, st);
+  nv->launch(ar, wr, wr, st);
+}
+
+ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st) {
   var[0]->launch(a, f, work, st);
-  var[1]->launch(a, work, work, st);
-  var[2]->launch(a, work, work, st);
-  var[3]->launch(a, work, work, st);
+  const int ns = slab_count(g, slab);
+  for (int s = 0; s < ns; ++s) {
+    void* ws = nullptr;
+    const PassArgs b = slab_args(g, a, slab, s, work, &ws);
+    var[1]->launch(b, ws, ws, st);
+    enqueue_zpass(g, var[2], b, ws, st);
+    var[3]->launch(b, ws, ws, st);
+  }
   var[4]->launch(a, work, u, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -237,6 +305,7 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   ups_plan_s* p = new ups_plan_s();
   p->prob = *prob;
   p->g = g;
+  p->slab = default_slab(g);
   for (int i = 0; i < 5; ++i) {
     p->var[i] = tuned_variant(kinds[i], g.f64, len[i], g);
     if (!p->var[i]) {
@@ -275,7 +344,7 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   if (e == hipSuccess) e = build_twiddles(g.f64, g.my, gb + g.off_twy, work, st);
   if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, gb + g.off_twz, work, st);
   if (e == hipSuccess)
-    e = build_green(g.f64, g.oz, g.oy, g.kx, g.px, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
+    e = build_green(g.f64, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "setup failed: %s", hipGetErrorString(e));
   plan->green = green;
   plan->work = work;
@@ -298,7 +367,7 @@ static ups_status check_io(ups_plan_t plan, const void* in, const void* out) {
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   ups_status s = check_io(plan, f, u);
   if (s != UPS_OK) return s;
-  s = enqueue_solve(plan->g, plan->var, plan->args, f, u, plan->work, static_cast<hipStream_t>(stream));
+  s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->work, static_cast<hipStream_t>(stream));
   return s == UPS_OK ? ok() : s;
 }
 
@@ -313,7 +382,10 @@ ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, vo
   void* o = pass == 4 ? out : plan ? plan->work : nullptr;
   ups_status s = check_io(plan, i, o);
   if (s != UPS_OK) return s;
-  plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
+  if (pass == 2)
+    enqueue_zpass(plan->g, plan->var[2], plan->args, o, static_cast<hipStream_t>(stream));
+  else
+    plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return ok();
@@ -326,7 +398,7 @@ ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long l
   if (plane) *plane = plan->g.plane;
   if (comp_stride) *comp_stride = plan->g.comp_w;
   if (ghat_offset) *ghat_offset = plan->g.off_ghat;
-  if (ghat_plane) *ghat_plane = (long long)plan->g.oz * plan->g.px;
+  if (ghat_plane) *ghat_plane = (long long)plan->g.kx * plan->g.gz;
   return ok();
 }
 
@@ -344,6 +416,28 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name) {
   plan->var[pass] = v;
   return ok();
 }
+
+int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap) {
+  if (pass < 0 || pass > 4 || (prec != UPS_F64 && prec != UPS_F32) || cap < 0 || (cap > 0 && !names)) return 0;
+  const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
+  int n = 0;
+  for (const PassVariant& v : pass_variants()) {
+    if (v.kind != kinds[pass] || v.is_f64 != (prec == UPS_F64 ? 1 : 0) || v.length != len) continue;
+    if (n < cap) names[n] = v.name;
+    ++n;
+  }
+  return n;
+}
+
+ups_status ups_plan_set_slab(ups_plan_t plan, int columns) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  if (columns < 0 || (columns > 0 && columns % 16 != 0))
+    return fail(UPS_ERR_INVALID_ARG, "slab width %d is not 0 or a positive multiple of 16", columns);
+  plan->slab = columns >= plan->g.kx ? 0 : columns;
+  return ok();
+}
+
+int ups_plan_slab(ups_plan_t plan) { return plan ? plan->slab : -1; }
 
 double ups_plan_model_bytes(ups_plan_t plan, int pass) {
   if (!plan || pass < -1 || pass > 4) return 0.0;

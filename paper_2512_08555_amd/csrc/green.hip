@@ -221,9 +221,9 @@ k_gemm_nt(const double* __restrict__ X, int ni, const double* __restrict__ Y, in
   }
 }
 
-// G_hat[iy][iz][kx] (pitch px, type T) = scale * D[iz][iy][kx]
+// G_hat[iy][kx][iz] (iz pitch gz, type T) = scale * D[iz][iy][kx]
 template <typename T>
-__global__ void k_store_ghat(const double* __restrict__ D, int kz, int ky, int kx, int px, double scale,
+__global__ void k_store_ghat(const double* __restrict__ D, int kz, int ky, int kx, int gz, double scale,
                              T* __restrict__ g) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long tot = (long long)kz * ky * kx;
@@ -231,7 +231,7 @@ __global__ void k_store_ghat(const double* __restrict__ D, int kz, int ky, int k
   const int x = int(idx % kx);
   const int y = int((idx / kx) % ky);
   const int z = int(idx / ((long long)kx * ky));
-  g[((long long)y * kz + z) * px + x] = T(scale * D[idx]);
+  g[((long long)y * kx + x) * gz + z] = T(scale * D[idx]);  // [iy][kx][iz]
 }
 
 // ---------------------------------------------------------------------------
@@ -285,7 +285,7 @@ GreenScratch green_scratch_layout(int kz, int ky, int kx) {
   } while (0)
 
 template <typename T>
-hipError_t build_green_t(int kz, int ky, int kx, int px, double h, int mx, int my, int mz, void* ghat,
+hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int my, int mz, void* ghat,
                          void* scratch, hipStream_t st) {
   const GreenScratch L = green_scratch_layout(kz, ky, kx);
   char* base = static_cast<char*>(scratch);
@@ -351,7 +351,7 @@ hipError_t build_green_t(int kz, int ky, int kx, int px, double h, int mx, int m
     const double scale = -(h * h) / (double(mx) * double(my) * double(mz));
     const long long tot = (long long)kz * ky * kx;
     hipLaunchKernelGGL((k_store_ghat<T>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
-                       P(L.off_G1), kz, ky, kx, px, scale, static_cast<T*>(ghat));
+                       P(L.off_G1), kz, ky, kx, gz, scale, static_cast<T*>(ghat));
     GCHECK(hipGetLastError());
   }
   // the host vectors above must outlive the copies
@@ -364,27 +364,40 @@ __global__ void k_twiddles(const double* __restrict__ src, int n, cx<T>* __restr
   if (i < n) dst[i] = cx<T>{T(src[2 * i]), T(src[2 * i + 1])};
 }
 
+// Twiddle table of one axis: entries m < M hold exp(-2 pi i m / M); the
+// kTw2 x kTw2 block after them holds T[a][b] = exp(-2 pi i (a b mod M) / M),
+// so a thread's run of twiddles w^(q k), k = 0, 1, ..., is one row (one base
+// address plus constant offsets) and a wave's w^(k l) over lanes l is one
+// contiguous row as well.
 template <typename T>
 hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
-  std::vector<double> tw(2 * (size_t)M);
+  const size_t n = twiddle_entries(M);
+  std::vector<double> tw(2 * n);
   for (int m = 0; m < M; ++m) {
     const cs_pair r = unit_root(-(long long)m, M);  // exp(-2 pi i m / M)
     tw[2 * m] = r.c;
     tw[2 * m + 1] = r.s;
   }
+  for (int a = 0; a < kTw2; ++a)
+    for (int b = 0; b < kTw2; ++b) {
+      const size_t i = (size_t)M + (size_t)a * kTw2 + b;
+      const long long m = ((long long)a * b) % M;
+      tw[2 * i] = tw[2 * m];
+      tw[2 * i + 1] = tw[2 * m + 1];
+    }
   GCHECK(hipMemcpyAsync(scratch, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL((k_twiddles<T>), dim3((M + 255) / 256), dim3(256), 0, st,
-                     static_cast<const double*>(scratch), M, static_cast<cx<T>*>(dst));
+  hipLaunchKernelGGL((k_twiddles<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const double*>(scratch), int(n), static_cast<cx<T>*>(dst));
   GCHECK(hipGetLastError());
   // the host vector must outlive the copy
   GCHECK(hipStreamSynchronize(st));
   return hipSuccess;
 }
 
-hipError_t build_green(bool f64, int kz, int ky, int kx, int px, double h, int mx, int my, int mz, void* ghat,
+hipError_t build_green(bool f64, int kz, int ky, int kx, int gz, double h, int mx, int my, int mz, void* ghat,
                        void* scratch, hipStream_t st) {
-  hipError_t e = f64 ? build_green_t<double>(kz, ky, kx, px, h, mx, my, mz, ghat, scratch, st)
-                     : build_green_t<float>(kz, ky, kx, px, h, mx, my, mz, ghat, scratch, st);
+  hipError_t e = f64 ? build_green_t<double>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
+                     : build_green_t<float>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
 }

@@ -19,12 +19,16 @@ GreenScratch green_scratch_layout(int kz, int ky, int kx);
 // Quadrature nodes t_j and weights w_j (dt folded in) on [0, T], and T.
 void lgf_quadrature(int n_max, std::vector<double>& t, std::vector<double>& w, double* T_out);
 
-// Ghat[iy][iz][kx] (pitch px) = h^2/(mx my mz) * DCT-I(G1) on the octant
+// Ghat[iy][kx][iz] (iz pitch gz) = h^2/(mx my mz) * DCT-I(G1) on the octant
 // kz x ky x kx = (mz/2+1) x (my/2+1) x (mx/2+1); waits for completion.
-hipError_t build_green(bool f64, int kz, int ky, int kx, int px, double h, int mx, int my, int mz,
+hipError_t build_green(bool f64, int kz, int ky, int kx, int gz, double h, int mx, int my, int mz,
                        void* ghat, void* scratch, hipStream_t st);
 
 // dst[m] = exp(-2 pi i m / M), m < M, complex float or double; waits.
+// Complex entries of one axis's twiddle table: M (exp(-2 pi i m / M)) plus a
+// kTw2 x kTw2 block of products (see build_twiddles_t).
+constexpr int kTw2 = 64;
+inline size_t twiddle_entries(int M) { return (size_t)M + (size_t)kTw2 * kTw2; }
 hipError_t build_twiddles(bool f64, int M, void* dst, void* scratch, hipStream_t st);
 
 }  // namespace ups

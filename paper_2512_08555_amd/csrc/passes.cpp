@@ -22,12 +22,20 @@ const std::vector<PassVariant>& pass_variants() {
 
 static inline int cdiv_ll(long long a, long long b) { return int((a + b - 1) / b); }
 
+const PassVariant* narrow_variant(const PassVariant& v) {
+  if (v.kind != PASS_ZCONV || v.nch != 0) return nullptr;
+  for (const PassVariant& w : pass_variants())
+    if (w.kind == PASS_ZCONV && w.nch == 0 && w.tile == 1 && w.is_f64 == v.is_f64 && w.length == v.length) return &w;
+  return nullptr;
+}
+
 // Blocks one launch of variant v needs for problem a (as the launchers in
 // passes_impl.hpp compute them).
 int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* gz) {
   const int per_line = 128 / (v.is_f64 ? 16 : 8);
-  const int H = per_line > v.tile ? per_line / v.tile : 1;
+  int H = per_line > v.tile ? per_line / v.tile : 1;
   const int ntiles = cdiv_ll(a.kx, v.tile);
+  if (v.kind == PASS_ZCONV && v.nch == 0 && H > ntiles) H = ntiles;  // as zwave_slots()
   *gy = 1;
   *gz = 1;
   switch (v.kind) {

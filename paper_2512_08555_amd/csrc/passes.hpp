@@ -4,7 +4,8 @@
 //   W[c][z][y][kx]   z < Nz, y < My, kx < Kx = Mx/2+1, row pitch px >= Kx,
 //                    plane = My * px; the x pass fills rows y < Ny, the
 //                    y-forward pass expands each plane in place to My rows.
-//   Ghat[iy][iz][kx] octant iy <= My/2, iz <= Mz/2, same pitch px (real T).
+//   Ghat[iy][kx][iz] octant iy <= My/2, iz <= Mz/2, iz fastest with pitch gz
+//                    (real T), so a z line's spectrum is contiguous.
 //   f, u             real T [c][Nz][Ny][Nx], contiguous.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -22,7 +23,8 @@ struct PassArgs {
   long long plane;       // my * px
   long long comp_w;      // nz * plane: component stride of W
   long long comp_f;      // nx * ny * nz: component stride of f and u
-  long long g_plane;     // (mz/2 + 1) * px: iy stride of Ghat
+  long long g_plane;     // kx * gz: iy stride of Ghat
+  int gz;                // iz pitch of Ghat (>= mz/2 + 1): kx stride
   int ncomp;
   const void* tw_x;      // exp(-2 pi i m / mx), m < mx
   const void* tw_y;
@@ -68,6 +70,9 @@ struct PassVariant {
 };
 
 const std::vector<PassVariant>& pass_variants();
+// The one-column-wide variant of the wave-per-line z kernel v (same length
+// and precision), or nullptr.
+const PassVariant* narrow_variant(const PassVariant& v);
 
 // helpers shared with the plan
 int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* gz);

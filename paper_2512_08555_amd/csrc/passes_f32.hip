@@ -1,7 +1,7 @@
 // Kernel instantiations: float, power-of-two padded lengths 32 .. 1024.
 // The first variant listed for a (pass, length) is the default (ordered by
 // measured time on MI355X for the 512^3 grid).
-#include "passes_impl.hpp"
+#include "zwave.hpp"
 
 namespace ups {
 
@@ -21,8 +21,10 @@ std::vector<PassVariant> variants_f32_pow2() {
       COL_VARIANTS(float, 8, 16, 16, 2),    // 128
       COL_VARIANTS(float, 16, 16, 16, 2),   // 256
       COL_VARIANTS(float, 16, 32, 16, 2),   // 512
+      ZW(float, 8, 8), ZW(float, 8, 4), ZW(float, 8, 1),
       YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
       YF(float, 32, 32, 8, 1), YF(float, 32, 32, 4, 1), YF(float, 32, 32, 4, 2),
+      ZW(float, 16, 8), ZW(float, 16, 4), ZW(float, 16, 1),
       ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
       ZC(float, 32, 32, 8, 1), ZC(float, 32, 32, 4, 1), ZC(float, 32, 32, 4, 2),
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),

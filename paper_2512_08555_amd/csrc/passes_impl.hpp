@@ -37,6 +37,8 @@ struct Split {
   static constexpr int D1 = Q / TL;      // P-DFTs per thread
   static constexpr int D3 = P / TL;      // Q-DFTs per thread
   static constexpr int E = D1 * P;       // values per thread
+  // twiddle runs are rows of the 64 x 64 product table
+  static_assert(P <= 64 && Q <= 64, "line split factors must be <= 64");
 };
 
 // per-thread spectrum of a line: w[d3][k2] = X[k1 + P k2], k1 = tl + TL d3
@@ -57,6 +59,13 @@ __device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) 
 template <typename T>
 __device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, unsigned idx) {
   return ld_at(tw, idx * unsigned(sizeof(cx<T>)));
+}
+// Row a of the product block that follows the M entries of a twiddle table:
+// row[b] = exp(-2 pi i (a b mod M) / M) for a, b < kTw2Row.
+constexpr int kTw2Row = 64;
+template <typename T>
+__device__ __forceinline__ const cx<T>* tw_row(const cx<T>* tw, int M, unsigned a) {
+  return tw + M + a * unsigned(kTw2Row);
 }
 
 template <typename T>
@@ -96,6 +105,7 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
   constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
   constexpr int RS = xfwd_row_stride<P, Q>();
   static_assert(RW % NCH == 0, "row groups");
+  static_assert(2 * (P - 1) < kTw2Row, "twiddle run w_M^(2 q k1) must fit a table row");
   __shared__ cx<T> lds[RG * RS];
 
   const int tid = threadIdx.x;
@@ -140,9 +150,10 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
       });
     }
     first_dft<P, -1>(v[d]);
+    const cx<T>* trow = tw_row(tw, 2 * L, unsigned(q));
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
-      v[d][k1] = cmul(v[d][k1], tw_at(tw, 2u * unsigned(q) * k1));  // w_L^{q k1} = w_M^{2 q k1}
+      v[d][k1] = cmul(v[d][k1], trow[2 * k1]);  // w_L^{q k1} = w_M^{2 q k1}
     });
   });
   static_for<0, NCH>([&](auto hh) {
@@ -217,6 +228,7 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
   constexpr int L = S::L, TL = S::TL, RG = RW / NCH;
   constexpr int VS = xinv_row_stride<P, Q>();
   static_assert(RW % NCH == 0, "row groups");
+  static_assert(2 * (Q - 1) < kTw2Row, "twiddle run w_M^(2 k1 n2) must fit a table row");
   __shared__ cx<T> lds[RG * VS];
 
   const int tid = threadIdx.x;
@@ -245,9 +257,10 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
       w[d][k2] = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw_at(tw, unsigned(k))));
     });
     dft<Q, +1>(w[d]);
+    const cx<T>* trow = tw_row(tw, 2 * L, unsigned(k1));
     static_for<1, Q>([&](auto nn) {
       constexpr int n2 = decltype(nn)::value;
-      w[d][n2] = cmulc(w[d][n2], tw_at(tw, 2u * unsigned(k1) * n2));
+      w[d][n2] = cmulc(w[d][n2], trow[2 * n2]);
     });
   });
   const int nx = a.nx;
@@ -344,9 +357,10 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
       });
     }
     first_dft<P, -1>(v);
+    const cx<T>* trow = tw_row(tw, S::L, unsigned(q));
     static_for<1, P>([&](auto kk) {
       constexpr int k1 = decltype(kk)::value;
-      v[k1] = cmul(v[k1], tw_at(tw, unsigned(q) * k1));
+      v[k1] = cmul(v[k1], trow[k1]);
     });
   });
   const int cl = c % CG;
@@ -393,9 +407,10 @@ __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, l
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + TL * d;
     dft<Q, +1>(w[d]);
+    const cx<T>* trow = tw_row(tw, S::L, unsigned(k1));
     static_for<1, Q>([&](auto nn) {
       constexpr int n2 = decltype(nn)::value;
-      w[d][n2] = cmulc(w[d][n2], tw_at(tw, unsigned(k1) * n2));
+      w[d][n2] = cmulc(w[d][n2], trow[n2]);
     });
   });
   const int cl = c % CG;
@@ -587,7 +602,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   const int ky = mp.line;
   const bool valid = kx0 + c < a.kx;
   const int iy = ky <= a.my - ky ? ky : a.my - ky;
-  const T* gbase = static_cast<const T*>(a.ghat) + iy * a.g_plane + kx0;
+  const T* gbase = static_cast<const T*>(a.ghat) + iy * a.g_plane + (long long)kx0 * a.gz;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
   const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
@@ -600,7 +615,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
       constexpr int k2 = decltype(kk)::value;
       const int kz = k1 + P * k2;
       const int iz = kz <= M - kz ? kz : M - kz;
-      const unsigned goff = (unsigned(iz) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(T));
+      const unsigned goff = (unsigned(c) * unsigned(a.gz) + unsigned(iz)) * unsigned(sizeof(T));
       // (the branch also keeps the scheduler from hoisting these loads,
       // which would hold 32 more registers through the forward transform)
       const T g = valid ? *reinterpret_cast<const T*>(reinterpret_cast<const char*>(gbase) + goff) : T(0);

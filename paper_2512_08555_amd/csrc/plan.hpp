@@ -13,7 +13,8 @@ struct PlanGeom {
   int nx, ny, nz;            // points
   int mx, my, mz;            // padded lengths
   int kx, oy, oz;            // stored x frequencies, octant extents in y and z
-  int px;                    // row pitch of W and G_hat (elements)
+  int px;                    // row pitch of W (elements)
+  int gz;                    // iz pitch of G_hat [iy][kx][iz] (elements)
   int ncomp;
   double h;
   long long plane, comp_w;   // W strides (complex elements)
@@ -31,8 +32,12 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);
 ups_status set_error(ups_status s, const char* msg);
-ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a,
+ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st);
+int default_slab(const PlanGeom& g);
+void enqueue_zpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st);
+int slab_count(const PlanGeom& g, int slab);
+PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* work, void** wslab);
 
 }  // namespace ups
 
@@ -44,5 +49,6 @@ struct ups_plan_s {
   void* work = nullptr;
   int device = 0;
   bool ready = false;
+  int slab = 0;              // kx columns per y/z/y slab (0: one slab)
   ups::PassArgs args{};
 };

@@ -1,0 +1,328 @@
+// Pass 3, one wavefront per z line: forward DFT along z (rows z < nz live),
+// times G_hat, inverse DFT, keep z < nz.
+//
+// A line of length M = 64 E lives in one wavefront, E values per lane, so
+// every exchange between FFT stages is wave-local: LDS traffic ordered by
+// the wave's own instruction stream, no workgroup barrier.  With 2E floats
+// of line data per lane the kernel needs far fewer registers than the
+// four-step column kernels, and more waves per SIMD hide the memory latency.
+//
+// Forward transform, n = l + 64 j (lane l, register j), k = k1 + E k2:
+//   stage 1  DFT_E over j (inputs j >= E/2 are the zero padding), times
+//            w_M^(l k1);
+//   the remaining DFT_64 over l, with l = l1 + A l2 (A = 64/E) and
+//   k2 = m1 + E m2, splits into
+//   stage 2  DFT_E over l2 on lane (k1, l1), times w_64^(l1 m1);
+//   stage 3  DFT_A over l1,
+// leaving lane L, register (r, m2) with X[L + 64 r + E^2 m2], r < E/A: for a
+// fixed register the lanes hold 64 consecutive frequencies, so the G_hat
+// loads of a wave are contiguous.  The inverse runs the mirrored steps with
+// n = n0 + A n', a = L + 64 r = b + E c, n' = e + E f:
+//   stage A  DFT_A over m2 (inverse), times conj w_M^(n0 a);
+//   stage B  DFT_E over c on lane (b, n0), times conj w_M^(A e b);
+//   stage C  DFT_E over b on lane (n0, e), only f < E/2 (rows n < M/2),
+// leaving lane L' = n0 + A e with rows L' + 64 f.
+//
+// A workgroup holds CW adjacent columns of one line (ky, component): it
+// stages the input tile (nz rows x CW columns) through LDS with coalesced
+// loads, each wave transforms one column using that column's LDS slot for
+// its exchanges, and the tile goes back through LDS to coalesced stores.
+// Exchanges move real parts, then imaginary parts, through the slot.  A run
+// of twiddles w^(k x), k < E, takes log2 E loads from the 64 x 64 product
+// block of the z table (rows k = 1, 2, 4, ...) and builds the other powers
+// as products.
+#pragma once
+#include "passes_impl.hpp"
+
+namespace ups {
+
+template <int E>
+struct ZWave {
+  static_assert(E >= 8 && 64 % E == 0, "lines of 64 E points, E in {8, 16, 32, 64}");
+  static constexpr int M = 64 * E;
+  static constexpr int A = 64 / E;     // stage-3 radix
+  static constexpr int E2 = E * E;
+  static constexpr int R3 = E / A;     // frequency groups per lane after stage 3
+  // LDS maps (floats), chosen so that the 32 lanes of each half-wave hit 32
+  // different banks:
+  //   exchange 1:  [k1][l], row stride S1 = 64 + 32/E
+  //   exchange 2 and inverse exchange 1:  [l1 or n0][a], row stride P2 >= E^2,
+  //                P2 = E (mod 32)
+  //   inverse exchange 2:  [e][E n0 + (b ^ swz(n0))], row stride 65,
+  //                swz(n0) = (E/2) [n0 >= A/2]
+  static constexpr int S1 = 64 + 32 / E;
+  static constexpr int P2 = E2 + ((E % 32) - (E2 % 32) + 32) % 32;
+  static constexpr int S4 = 65;
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int xfloats = cmax(cmax(E * S1, A * P2), (E - 1) * S4 + 64);
+};
+
+// Complex elements per LDS column slot: room for the nz <= M/2 tile rows and
+// for one exchange (floats), with slot stride = 16 / CW (mod 16) so that the
+// 64-bit tile accesses of the CW columns fall in different banks.
+template <int E, int CW>
+constexpr int zwave_slot() {
+  int need = ZWave<E>::cmax(32 * E, (ZWave<E>::xfloats + 1) / 2);
+  const int r = (16 / CW) % 16;
+  while (need % 16 != r) ++need;
+  return need;
+}
+
+__device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
+
+// v[k] *= w^(k x) (conjugated if CONJ) for k = 1 .. K-1, given pw(j) =
+// w^(2^j x): the other powers are products of earlier ones (k = 2^j + r,
+// w^(k x) = w^(2^j x) w^(r x)), so a run of K - 1 twiddles costs log2 K
+// table loads.
+template <int K, bool CONJ, typename T, typename PW>
+__device__ __forceinline__ void twiddle_run(cx<T>* v, PW pw) {
+  static_assert((K & (K - 1)) == 0, "power-of-two run length");
+  cx<T> p[K];
+  static_for<1, K>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    constexpr int hb = 1 << (31 - __builtin_clz(k));   // largest power of two <= k
+    if constexpr (hb == k) {
+      p[k] = pw(31 - __builtin_clz(k));
+    } else {
+      p[k] = cmul(p[hb], p[k - hb]);
+    }
+    v[k] = CONJ ? cmulc(v[k], p[k]) : cmul(v[k], p[k]);
+  });
+}
+
+// Move the E values of every lane through the slot xf (T[]), real parts
+// first: value i of this lane is stored at xf[waddr(i)] and value i
+// afterwards is loaded from xf[raddr(i)].  All lanes of the wave take part;
+// LDS accesses of one wave complete in order, so no barrier is needed.
+template <typename T, int E, typename WA, typename RA>
+__device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA raddr) {
+  T o[E];
+  wave_fence();
+  static_for<0, E>([&](auto ii) { constexpr int i = decltype(ii)::value; xf[waddr(i)] = v[i].re; });
+  wave_fence();
+  static_for<0, E>([&](auto ii) { constexpr int i = decltype(ii)::value; o[i] = xf[raddr(i)]; });
+  wave_fence();
+  static_for<0, E>([&](auto ii) { constexpr int i = decltype(ii)::value; xf[waddr(i)] = v[i].im; });
+  wave_fence();
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    v[i].re = o[i];
+    v[i].im = xf[raddr(i)];
+  });
+  wave_fence();
+}
+
+// Tiles per 128-byte line group of the block map, capped by the number of
+// tiles (a narrow launch over a few columns gets no empty slots).
+template <typename T, int CW>
+__host__ __device__ inline int zwave_slots(int ntiles) {
+  const int h = tile_slots<T, CW>();
+  return h > ntiles ? ntiles : h;
+}
+
+template <typename T, int E, int CW>
+__device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
+  using Z = ZWave<E>;
+  constexpr int M = Z::M, A = Z::A, E2 = Z::E2, R3 = Z::R3;
+  constexpr int S1 = Z::S1, P2 = Z::P2, S4 = Z::S4;
+  constexpr int CS = zwave_slot<E, CW>();
+  constexpr unsigned CB = sizeof(cx<T>);
+  __shared__ cx<T> tile[CW * CS];
+
+  const int ntiles = (a.kx + CW - 1) / CW;
+  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, zwave_slots<T, CW>(ntiles));
+  if (!mp.active) return;  // uniform over the workgroup, before any barrier
+  const int t = threadIdx.x;
+  const int lane = t & 63, c = t >> 6;
+  const int kx0 = mp.tile * CW;
+  const int ky = mp.line;
+  cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
+  const int nz = a.nz;
+  const bool full = nz == M / 2;
+
+  // ---- coalesced tile load: thread (tc, tr) moves rows tr + 64 i of column tc
+  const int tc = t % CW, tr = t / CW;
+  const bool tvalid = kx0 + tc < a.kx;
+  const int tcl = tvalid ? tc : a.kx - 1 - kx0;  // in-bounds column for the loads
+  const unsigned toff = (unsigned(tr) * unsigned(a.plane) + unsigned(tcl)) * CB;
+  cx<T>* tslot = tile + tc * CS;
+  if (full) {
+    cx<T> ld[E / 2];
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      ld[i] = ld_at(ubase + (long long)(64 * i) * a.plane, toff);
+    });
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      tslot[tr + 64 * i] = ld[i];
+    });
+  } else {
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const int row = tr + 64 * i;
+      const int rowc = row < nz ? row : nz - 1;  // clamped: loads stay in bounds
+      const cx<T> val = ld_at(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB);
+      tslot[row] = row < nz ? val : zero_c<T>();
+    });
+  }
+  __syncthreads();
+
+  // ---- wave c: the line of column kx0 + c
+  cx<T>* slot = tile + c * CS;
+  T* xf = reinterpret_cast<T*>(slot);
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
+  cx<T> v[E];
+  static_for<0, E / 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    v[j] = slot[lane + 64 * j];
+  });
+  // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
+  dft_half_in<E, -1>(v);
+  twiddle_run<E, false>(v, [&](int j) { return tw_row(tw, M, 1u << j)[lane]; });
+  // exchange 1: (l, k1) at k1 S1 + l; lane (k1, l1) reads l2 at k1 S1 + l1 + A l2
+  {
+    const int k1 = lane % E, l1 = lane / E;
+    const int rb = k1 * S1 + l1;
+    wave_exchange<T, E>(v, xf, [&](int i) { return lane + i * S1; }, [&](int i) { return rb + A * i; });
+  }
+  // stage 2: DFT_E over l2, times w_64^(l1 m1) = T[E l1][m1]
+  dft<E, -1>(v);
+  {
+    const int el1 = E * (lane / E);
+    twiddle_run<E, false>(v, [&](int j) { return tw_row(tw, M, 1u << j)[el1]; });
+  }
+  // exchange 2: (a = k1 + E m1, l1) at l1 P2 + a; lane L reads register
+  // r A + l1 (a = L + 64 r)
+  {
+    const int wb = (lane / E) * P2 + lane % E;
+    wave_exchange<T, E>(v, xf, [&](int i) { return wb + E * i; },
+                        [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); });
+  }
+  // stage 3 and G_hat: lane L, register r A + m2 holds kz = L + 64 r + E^2 m2
+  static_for<0, R3>([&](auto rr) {
+    constexpr int r = decltype(rr)::value;
+    dft<A, -1>(&v[r * A]);
+  });
+  {
+    const int cg = (kx0 + c < a.kx) ? c : a.kx - 1 - kx0;
+    const int iy = ky <= a.my - ky ? ky : a.my - ky;
+    const T* gline = static_cast<const T*>(a.ghat) + iy * a.g_plane + (long long)(kx0 + cg) * a.gz;
+    static_for<0, R3>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      static_for<0, A>([&](auto mm) {
+        constexpr int m2 = decltype(mm)::value;
+        const int kz = lane + 64 * r + E2 * m2;
+        const int iz = kz <= M - kz ? kz : M - kz;
+        v[r * A + m2] = scale(v[r * A + m2], gline[iz]);
+      });
+    });
+  }
+  // inverse stage A: DFT_A over m2, times conj w_M^(n0 a), a = L + 64 r:
+  // w_M^(n0 L) = T[n0][L] and the constant w_M^(64 n0 r)
+  {
+    // w_M^(n0 L) for n0 < A, shared by the R3 groups
+    cx<T> q[A];
+    static_for<1, A>([&](auto nn) {
+      constexpr int n0 = decltype(nn)::value;
+      constexpr int hb = 1 << (31 - __builtin_clz(n0));
+      if constexpr (hb == n0) q[n0] = tw_row(tw, M, unsigned(n0))[lane];
+      else q[n0] = cmul(q[hb], q[n0 - hb]);
+    });
+    static_for<0, R3>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      dft<A, +1>(&v[r * A]);
+      static_for<1, A>([&](auto nn) {
+        constexpr int n0 = decltype(nn)::value;
+        v[r * A + n0] = twiddle_c<(long long)64 * r * n0, M, +1>(cmulc(v[r * A + n0], q[n0]));
+      });
+    });
+  }
+  // inverse exchange 1: (a, n0) at n0 P2 + a; lane (b, n0) reads c at
+  // n0 P2 + b + E c
+  {
+    const int rb = (lane / E) * P2 + lane % E;
+    wave_exchange<T, E>(v, xf, [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); },
+                        [&](int i) { return rb + E * i; });
+  }
+  // inverse stage B: DFT_E over c, times conj w_M^(A e b) = T[A e][b]
+  dft<E, +1>(v);
+  {
+    const int ab = A * (lane % E);
+    twiddle_run<E, true>(v, [&](int j) { return tw_row(tw, M, 1u << j)[ab]; });
+  }
+  // inverse exchange 2: (b, n0, e) at e S4 + E n0 + (b ^ swz(n0)); lane
+  // (n0, e) = n0 + A e reads b
+  {
+    constexpr int HE = E / 2;
+    const int b = lane % E, n0 = lane / E;
+    const int wb = E * n0 + (b ^ (n0 >= A / 2 ? HE : 0));
+    const int n0r = lane % A, er = lane / A;
+    const int sw = n0r >= A / 2 ? HE : 0;
+    const int rlo = er * S4 + E * n0r + sw;   // b < E/2: b ^ sw = b + sw
+    const int rhi = er * S4 + E * n0r - sw;   // b >= E/2: b ^ sw = b - sw
+    wave_exchange<T, E>(v, xf, [&](int i) { return wb + S4 * i; },
+                        [&](int i) { return (i < HE ? rlo : rhi) + i; });
+  }
+  // inverse stage C, rows lane + 64 f (f < E/2) back into the slot
+  dft_half_out<E, +1>(v);
+  wave_fence();
+  static_for<0, E / 2>([&](auto ff) {
+    constexpr int f = decltype(ff)::value;
+    slot[lane + 64 * f] = v[f];
+  });
+  __syncthreads();
+
+  // ---- coalesced tile store, rows z < nz
+  if (tvalid) {
+    if (full) {
+      static_for<0, E / 2>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        st_at(ubase + (long long)(64 * i) * a.plane, toff, tslot[tr + 64 * i]);
+      });
+    } else {
+      // rows >= nz write row nz - 1 again (the same value): no per-row branch
+      static_for<0, E / 2>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const int row = tr + 64 * i;
+        const int rowc = row < nz ? row : nz - 1;
+        st_at(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB, tslot[rowc]);
+      });
+    }
+  }
+}
+
+template <typename T, int E, int CW>
+__global__ void __launch_bounds__(64 * CW) k_zwave(cx<T>* __restrict__ W, PassArgs a) {
+  zwave_body<T, E, CW>(W, a, blockIdx.x);
+}
+template <typename T, int E, int CW>
+__global__ void __launch_bounds__(64 * CW) k_zwave_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  zwave_body<T, E, CW>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+}
+
+template <typename T, int E, int CW>
+inline unsigned zwave_blocks(const PassArgs& a) {
+  return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, zwave_slots<T, CW>(cdiv(a.kx, CW)));
+}
+template <typename T, int E, int CW>
+void launch_zwave(const PassArgs& a, const void*, void* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_zwave<T, E, CW>), dim3(zwave_blocks<T, E, CW>(a)), dim3(64 * CW), 0, s,
+                     static_cast<cx<T>*>(out), a);
+}
+template <typename T, int E, int CW>
+void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_zwave_g<T, E, CW>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+}
+
+// P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
+// wave-per-line family.
+#define ZW(T, E, CW)                                                                              \
+  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
+              int(sizeof(cx<T>)) * CW * zwave_slot<E, CW>(), "zconv_" #T "_w" #E "_c" #CW,        \
+              &launch_zwave<T, E, CW>, &launchg_zwave<T, E, CW>}
+
+}  // namespace ups

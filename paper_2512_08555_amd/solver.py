@@ -135,6 +135,15 @@ class Plan:
     def set_kernel(self, k, name):
         capi.check(capi.lib().ups_plan_set_kernel(self._h, int(k), name.encode()))
 
+    @property
+    def slab(self):
+        """kx columns per slab of the column passes (0: one slab)."""
+        return capi.lib().ups_plan_slab(self._h)
+
+    @slab.setter
+    def slab(self, columns):
+        capi.check(capi.lib().ups_plan_set_slab(self._h, int(columns)))
+
     def model_bytes(self, k=-1):
         return capi.lib().ups_plan_model_bytes(self._h, int(k))
 
@@ -148,15 +157,17 @@ class Plan:
 
     def ghat(self):
         """Copy of G_hat (octant [iz, iy, kx], plan precision) read from the green
-        buffer, for inspection."""
+        buffer, for inspection.  The buffer holds it as [iy][kx][iz] with the iz
+        pitch ghat_plane / kx."""
         lay = self.layout()
         mz, my, mx = self.padded
         oz, oy, kx = mz // 2 + 1, my // 2 + 1, mx // 2 + 1
         esz = 8 if self.prec == "f64" else 4
+        gz = lay["ghat_plane"] // kx
         n = oy * lay["ghat_plane"]
         raw = self.green[lay["ghat_offset"]: lay["ghat_offset"] + n * esz].view(self.dtype)
-        g = raw.view(oy, oz, lay["pitch"])[:, :, :kx]
-        return g.permute(1, 0, 2).contiguous()
+        g = raw.view(oy, kx, gz)[:, :, :oz]
+        return g.permute(2, 0, 1).contiguous()
 
     def work_complex(self):
         """The work buffer viewed as complex [c][z][y][pitch] (plan precision)."""
@@ -168,6 +179,16 @@ class Plan:
         w = self.work[: n * esz].view(ct)
         my = lay["plane"] // lay["pitch"]
         return w.view(self.ncomp, nz, my, lay["pitch"])
+
+
+def kernel_variants(k, prec, length):
+    """Names of the compiled kernel variants of pass k for a padded length."""
+    L = capi.lib()
+    p = capi.UPS_F64 if prec == "f64" else capi.UPS_F32
+    n = L.ups_kernel_variants(int(k), p, int(length), None, 0)
+    arr = (C.c_char_p * max(n, 1))()
+    L.ups_kernel_variants(int(k), p, int(length), arr, n)
+    return [arr[i].decode() for i in range(n)]
 
 
 def solve(f, h, prec=None, pad=None):

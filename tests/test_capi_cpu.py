@@ -188,3 +188,29 @@ def test_autotune_requires_setup():
     assert L.ups_autotune(h, None, 10.0) == capi.UPS_ERR_STATE
     assert L.ups_autotune(None, None, 10.0) == capi.UPS_ERR_INVALID_ARG
     L.ups_plan_destroy(h)
+
+
+def test_kernel_variant_listing():
+    _lib_or_skip()
+    from paper_2512_08555_amd.solver import kernel_variants
+    L = capi.lib()
+    for k in range(5):
+        for prec in ("f32", "f64"):
+            names = kernel_variants(k, prec, 512)
+            assert names, (k, prec)
+            assert len(set(names)) == len(names)
+    z = kernel_variants(2, "f32", 1024)
+    assert any(n.startswith("zconv_float_w16") for n in z)
+    assert L.ups_kernel_variants(5, capi.UPS_F32, 512, None, 0) == 0
+    assert L.ups_kernel_variants(0, 7, 512, None, 0) == 0
+    assert L.ups_kernel_variants(0, capi.UPS_F32, 33, None, 0) == 0
+    # a plan's default is the first variant listed
+    p = make_problem((512, 8, 8), 1 / 512, prec="f32", pad=(1024, 32, 32))
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    assert L.ups_plan_kernel(h, 2).decode() in z
+    assert L.ups_plan_set_slab(h, 7) == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_plan_set_slab(h, 16) == capi.UPS_OK
+    assert L.ups_plan_slab(h) == 16
+    L.ups_plan_destroy(h)
+    assert L.ups_plan_slab(None) == -1
