@@ -123,7 +123,7 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
       if (spent > budget_ms && v != plan->var[k]) continue;
       const int reps = 5;
       auto run = [&]() {
-        if (k == 2) enqueue_zpass(g, v, plan->args, work, st);
+        if (k >= 1 && k <= 3) enqueue_colpass(g, v, plan->args, work, st);
         else v->launch(plan->args, work, work, st);
       };
       run();  // warm-up

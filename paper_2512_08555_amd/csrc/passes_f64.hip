@@ -1,7 +1,7 @@
 // Kernel instantiations: double, power-of-two padded lengths 32 .. 1024.
 // The first variant listed for a (pass, length) is the default (ordered by
 // measured time on MI355X for the 256^3 and 512^3 grids).
-#include "passes_impl.hpp"
+#include "zwave.hpp"
 
 namespace ups {
 
@@ -19,11 +19,15 @@ std::vector<PassVariant> variants_f64() {
       COL_VARIANTS(double, 8, 16, 8, 2),
       COL_VARIANTS(double, 16, 16, 8, 2),
       YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
+      ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZWG(double, 8, 4), ZW(double, 8, 1),
       ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
       YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
+      YF(double, 16, 32, 2, 1), YI(double, 16, 32, 2, 1),
       YF(double, 32, 32, 8, 2), YF(double, 32, 32, 8, 4),   // 1024
+      ZW(double, 16, 8), ZWG(double, 16, 8), ZW(double, 16, 4), ZWG(double, 16, 4), ZW(double, 16, 1),
       ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
+      YF(double, 32, 32, 2, 1), YI(double, 32, 32, 2, 1),
   };
 }
 

@@ -476,6 +476,14 @@ constexpr int tile_slots() {
   return per_line > C ? per_line / C : 1;
 }
 
+// Slots per group, capped by the number of tiles: a launch over a few
+// columns (the remainder of an aligned split) gets no empty slots.
+template <typename T, int C>
+__host__ __device__ inline int col_slots(int ntiles) {
+  constexpr int h = tile_slots<T, C>();
+  return h > ntiles ? ntiles : h;
+}
+
 struct ColMap {
   int tile, line, comp;   // line = z (y passes) or ky (z pass)
   bool active;
@@ -533,7 +541,7 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, tile_slots<T, C>());
+  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, col_slots<T, C>((a.kx + C - 1) / C));
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int kx0 = mp.tile * C;
   const int z = mp.line, comp = mp.comp;
@@ -564,7 +572,7 @@ __device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs&
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
-  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, tile_slots<T, C>());
+  const ColMap mp = ymap(blin, (a.kx + C - 1) / C, a.nz, a.ncomp, col_slots<T, C>((a.kx + C - 1) / C));
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int kx0 = mp.tile * C;
   const int z = mp.line, comp = mp.comp;
@@ -594,7 +602,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   static_assert(C % NCH == 0, "column groups");
   __shared__ cx<T> lds[col_lds_elems<P, Q, C, NCH>()];
   const int ntiles = (a.kx + C - 1) / C;
-  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, tile_slots<T, C>());
+  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, col_slots<T, C>(ntiles));
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int tid = threadIdx.x;
   const int c = tid % C, tl = tid / C;
@@ -636,11 +644,11 @@ __host__ __device__ inline int cdiv(long long a, long long b) { return int((a + 
 
 template <typename T, int C>
 inline unsigned zconv_blocks(const PassArgs& a) {
-  return zmap_blocks(cdiv(a.kx, C), a.my, a.ncomp, tile_slots<T, C>());
+  return zmap_blocks(cdiv(a.kx, C), a.my, a.ncomp, col_slots<T, C>(cdiv(a.kx, C)));
 }
 template <typename T, int C>
 inline unsigned ypass_blocks(const PassArgs& a) {
-  return ymap_blocks(cdiv(a.kx, C), a.nz, a.ncomp, tile_slots<T, C>());
+  return ymap_blocks(cdiv(a.kx, C), a.nz, a.ncomp, col_slots<T, C>(cdiv(a.kx, C)));
 }
 
 // The problem of this block; *lin = block index inside the problem.  Blocks

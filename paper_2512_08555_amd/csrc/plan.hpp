@@ -35,7 +35,7 @@ ups_status set_error(ups_status s, const char* msg);
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st);
 int default_slab(const PlanGeom& g);
-void enqueue_zpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st);
+void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st);
 int slab_count(const PlanGeom& g, int slab);
 PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* work, void** wslab);
 

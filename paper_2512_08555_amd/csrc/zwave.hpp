@@ -112,15 +112,9 @@ __device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA
   wave_fence();
 }
 
-// Tiles per 128-byte line group of the block map, capped by the number of
-// tiles (a narrow launch over a few columns gets no empty slots).
-template <typename T, int CW>
-__host__ __device__ inline int zwave_slots(int ntiles) {
-  const int h = tile_slots<T, CW>();
-  return h > ntiles ? ntiles : h;
-}
-
-template <typename T, int E, int CW>
+// GP: load this lane's G_hat values at the start (they then share the
+// latency of the tile loads) instead of after the forward transform.
+template <typename T, int E, int CW, bool GP>
 __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, E2 = Z::E2, R3 = Z::R3;
@@ -130,7 +124,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   __shared__ cx<T> tile[CW * CS];
 
   const int ntiles = (a.kx + CW - 1) / CW;
-  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, zwave_slots<T, CW>(ntiles));
+  const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, col_slots<T, CW>(ntiles));
   if (!mp.active) return;  // uniform over the workgroup, before any barrier
   const int t = threadIdx.x;
   const int lane = t & 63, c = t >> 6;
@@ -139,6 +133,22 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
   const int nz = a.nz;
   const bool full = nz == M / 2;
+  // G_hat line of this wave's column: kz = lane + 64 r + E^2 m2 reads
+  // octant row iz = min(kz, M - kz)
+  const T* gline;
+  {
+    const int cg = (kx0 + c < a.kx) ? c : a.kx - 1 - kx0;
+    const int iy = ky <= a.my - ky ? ky : a.my - ky;
+    gline = static_cast<const T*>(a.ghat) + iy * a.g_plane + (long long)(kx0 + cg) * a.gz;
+  }
+  auto gload = [&](int i) {
+    const int kz = lane + 64 * (i / A) + E2 * (i % A);
+    return gline[kz <= M - kz ? kz : M - kz];
+  };
+  T gpre[GP ? E : 1];
+  if constexpr (GP) {
+    static_for<0, E>([&](auto ii) { gpre[decltype(ii)::value] = gload(decltype(ii)::value); });
+  }
 
   // ---- coalesced tile load: thread (tc, tr) moves rows tr + 64 i of column tc
   const int tc = t % CW, tr = t / CW;
@@ -203,20 +213,11 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     constexpr int r = decltype(rr)::value;
     dft<A, -1>(&v[r * A]);
   });
-  {
-    const int cg = (kx0 + c < a.kx) ? c : a.kx - 1 - kx0;
-    const int iy = ky <= a.my - ky ? ky : a.my - ky;
-    const T* gline = static_cast<const T*>(a.ghat) + iy * a.g_plane + (long long)(kx0 + cg) * a.gz;
-    static_for<0, R3>([&](auto rr) {
-      constexpr int r = decltype(rr)::value;
-      static_for<0, A>([&](auto mm) {
-        constexpr int m2 = decltype(mm)::value;
-        const int kz = lane + 64 * r + E2 * m2;
-        const int iz = kz <= M - kz ? kz : M - kz;
-        v[r * A + m2] = scale(v[r * A + m2], gline[iz]);
-      });
-    });
-  }
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    if constexpr (GP) v[i] = scale(v[i], gpre[i]);
+    else v[i] = scale(v[i], gload(i));
+  });
   // inverse stage A: DFT_A over m2, times conj w_M^(n0 a), a = L + 64 r:
   // w_M^(n0 L) = T[n0][L] and the constant w_M^(64 n0 r)
   {
@@ -291,38 +292,42 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   }
 }
 
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool GP>
 __global__ void __launch_bounds__(64 * CW) k_zwave(cx<T>* __restrict__ W, PassArgs a) {
-  zwave_body<T, E, CW>(W, a, blockIdx.x);
+  zwave_body<T, E, CW, GP>(W, a, blockIdx.x);
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool GP>
 __global__ void __launch_bounds__(64 * CW) k_zwave_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  zwave_body<T, E, CW>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  zwave_body<T, E, CW, GP>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 
-template <typename T, int E, int CW>
+template <typename T, int CW>
 inline unsigned zwave_blocks(const PassArgs& a) {
-  return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, zwave_slots<T, CW>(cdiv(a.kx, CW)));
+  return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, col_slots<T, CW>(cdiv(a.kx, CW)));
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool GP>
 void launch_zwave(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave<T, E, CW>), dim3(zwave_blocks<T, E, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_zwave<T, E, CW, GP>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool GP>
 void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave_g<T, E, CW>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+  hipLaunchKernelGGL((k_zwave_g<T, E, CW, GP>), dim3(nblocks), dim3(64 * CW), 0, s, g);
 }
 
 // P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
-// wave-per-line family.
+// wave-per-line family; the "_g" variants load G_hat at the start.
 #define ZW(T, E, CW)                                                                              \
   PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
               int(sizeof(cx<T>)) * CW * zwave_slot<E, CW>(), "zconv_" #T "_w" #E "_c" #CW,        \
-              &launch_zwave<T, E, CW>, &launchg_zwave<T, E, CW>}
+              &launch_zwave<T, E, CW, false>, &launchg_zwave<T, E, CW, false>}
+#define ZWG(T, E, CW)                                                                             \
+  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
+              int(sizeof(cx<T>)) * CW * zwave_slot<E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_g",   \
+              &launch_zwave<T, E, CW, true>, &launchg_zwave<T, E, CW, true>}
 
 }  // namespace ups
