@@ -238,7 +238,8 @@ static PassArgs column_range(const PlanGeom& g, const PassArgs& a, int k0, int w
 // MI355X: 20% for the y-forward pass at 512^3): the launch covers a multiple
 // of 8 x (columns per 128-byte line) columns, and the few columns left over
 // go to the narrowest variant of the same pass.
-void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st) {
+void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
+                     const SideStream* side) {
   const int align = 8 * (128 / int(2 * g.elem));
   const PassVariant* nv = narrow_variant(*v);
   const int kmain = a.kx / align * align;
@@ -250,20 +251,29 @@ void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a,
   void* wr = nullptr;
   const PassArgs am = column_range(g, a, 0, kmain, ws, &wm);
   const PassArgs ar = column_range(g, a, kmain, a.kx - kmain, ws, &wr);
-  v->launch(am, wm, wm, st);
-  nv->launch(ar, wr, wr, st);
+  if (side && side->s) {
+    hipEventRecord(side->fork, st);
+    hipStreamWaitEvent(side->s, side->fork, 0);
+    nv->launch(ar, wr, wr, side->s);
+    hipEventRecord(side->join, side->s);
+    v->launch(am, wm, wm, st);
+    hipStreamWaitEvent(st, side->join, 0);
+  } else {
+    v->launch(am, wm, wm, st);
+    nv->launch(ar, wr, wr, st);
+  }
 }
 
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
-                         const void* f, void* u, void* work, hipStream_t st) {
+                         const void* f, void* u, void* work, hipStream_t st, const SideStream* side) {
   var[0]->launch(a, f, work, st);
   const int ns = slab_count(g, slab);
   for (int s = 0; s < ns; ++s) {
     void* ws = nullptr;
     const PassArgs b = slab_args(g, a, slab, s, work, &ws);
-    enqueue_colpass(g, var[1], b, ws, st);
-    enqueue_colpass(g, var[2], b, ws, st);
-    enqueue_colpass(g, var[3], b, ws, st);
+    enqueue_colpass(g, var[1], b, ws, st, side);
+    enqueue_colpass(g, var[2], b, ws, st, side);
+    enqueue_colpass(g, var[3], b, ws, st, side);
   }
   var[4]->launch(a, work, u, st);
   hipError_t e = hipGetLastError();
@@ -272,6 +282,17 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
 }
 
 }  // namespace ups
+
+ups_plan_s::~ups_plan_s() {
+  if (!side.s) return;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  if (have && cur != device) hipSetDevice(device);
+  hipEventDestroy(side.fork);
+  hipEventDestroy(side.join);
+  hipStreamDestroy(side.s);
+  if (have && cur != device) hipSetDevice(cur);
+}
 
 // ============================================================================
 extern "C" {
@@ -347,6 +368,12 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   if (e == hipSuccess)
     e = build_green(g.f64, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "setup failed: %s", hipGetErrorString(e));
+  if (!plan->side.s) {
+    e = hipStreamCreateWithFlags(&plan->side.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->side.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->side.join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "side stream: %s", hipGetErrorString(e));
+  }
   plan->green = green;
   plan->work = work;
   plan->device = dev;
@@ -368,7 +395,8 @@ static ups_status check_io(ups_plan_t plan, const void* in, const void* out) {
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   ups_status s = check_io(plan, f, u);
   if (s != UPS_OK) return s;
-  s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->work, static_cast<hipStream_t>(stream));
+  s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->work, static_cast<hipStream_t>(stream),
+                    &plan->side);
   return s == UPS_OK ? ok() : s;
 }
 
@@ -384,7 +412,7 @@ ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, vo
   ups_status s = check_io(plan, i, o);
   if (s != UPS_OK) return s;
   if (pass >= 1 && pass <= 3)
-    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream));
+    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream), &plan->side);
   else
     plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();

@@ -19,8 +19,8 @@ std::vector<PassVariant> variants_f64() {
       COL_VARIANTS(double, 8, 16, 8, 2),
       COL_VARIANTS(double, 16, 16, 8, 2),
       YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
-      ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZWG(double, 8, 4), ZW(double, 8, 1),
       ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
+      ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZWG(double, 8, 4), ZW(double, 8, 1),
       YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
       YF(double, 16, 32, 2, 1), YI(double, 16, 32, 2, 1),
       YF(double, 32, 32, 8, 2), YF(double, 32, 32, 8, 4),   // 1024

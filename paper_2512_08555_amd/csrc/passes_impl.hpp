@@ -68,6 +68,25 @@ __device__ __forceinline__ const cx<T>* tw_row(const cx<T>* tw, int M, unsigned 
   return tw + M + a * unsigned(kTw2Row);
 }
 
+// v[k] *= w^(k x) (conjugated if CONJ) for k = 1 .. K-1, given pw(j) =
+// w^(2^j x): the other powers are products of earlier ones (k = 2^j + r,
+// w^(k x) = w^(2^j x) w^(r x)), so a run of K - 1 twiddles costs
+// ceil(log2 K) table loads and a few products (error a few ulp).
+template <int K, bool CONJ, typename T, typename PW>
+__device__ __forceinline__ void twiddle_run(cx<T>* v, PW pw) {
+  cx<T> p[K];
+  static_for<1, K>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    constexpr int hb = 1 << (31 - __builtin_clz(k));   // largest power of two <= k
+    if constexpr (hb == k) {
+      p[k] = pw(31 - __builtin_clz(k));
+    } else {
+      p[k] = cmul(p[hb], p[k - hb]);
+    }
+    v[k] = CONJ ? cmulc(v[k], p[k]) : cmul(v[k], p[k]);
+  });
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> zero_c() { return cx<T>{T(0), T(0)}; }
 
@@ -151,10 +170,8 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
     }
     first_dft<P, -1>(v[d]);
     const cx<T>* trow = tw_row(tw, 2 * L, unsigned(q));
-    static_for<1, P>([&](auto kk) {
-      constexpr int k1 = decltype(kk)::value;
-      v[d][k1] = cmul(v[d][k1], trow[2 * k1]);  // w_L^{q k1} = w_M^{2 q k1}
-    });
+    // w_L^{q k1} = w_M^{2 q k1}
+    twiddle_run<P, false>(v[d], [&](int j) { return trow[2 << j]; });
   });
   static_for<0, NCH>([&](auto hh) {
     constexpr int h = decltype(hh)::value;
@@ -196,6 +213,7 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
     }
     __syncthreads();
     if (mine && valid) {
+      const cx<T> wtl = tw_at(tw, unsigned(tl));
       // k = tl + TL i for i < L/TL, then k = L on lane tl = 0
       static_for<0, L / TL + 1>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
@@ -206,7 +224,10 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
           const cx<T> zm = conj(my[kk == 0 ? 0 : L - kk]);
           const cx<T> e = scale(zk + zm, T(0.5));
           const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));  // (Z - conj Z')/(2i)
-          dst[kk] = e + cmul(o, tw_at(tw, unsigned(kk)));
+          // w_M^kk = w_M^tl w_M^(TL i) (kk = L: w_M^L = -i... as a constant)
+          const cx<T> wk = i < L / TL ? twiddle_c<(long long)TL * i, 2 * L, -1>(wtl)
+                                      : twiddle_c<(long long)L, 2 * L, -1>(cx<T>{T(1), T(0)});
+          dst[kk] = e + cmul(o, wk);
         }
       });
     }
@@ -249,19 +270,18 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + TL * d;
+    const cx<T> wk1 = tw_at(tw, unsigned(k1));
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
       const int k = k1 + P * k2;
       const cx<T> xk = src[k];
       const cx<T> xm = conj(src[L - k]);
-      w[d][k2] = (xk + xm) + mul_i<+1>(cmulc(xk - xm, tw_at(tw, unsigned(k))));
+      // conj w_M^k = conj w_M^k1 conj w_M^(P k2)
+      w[d][k2] = (xk + xm) + mul_i<+1>(twiddle_c<(long long)P * k2, 2 * L, +1>(cmulc(xk - xm, wk1)));
     });
     dft<Q, +1>(w[d]);
     const cx<T>* trow = tw_row(tw, 2 * L, unsigned(k1));
-    static_for<1, Q>([&](auto nn) {
-      constexpr int n2 = decltype(nn)::value;
-      w[d][n2] = cmulc(w[d][n2], trow[2 * n2]);
-    });
+    twiddle_run<Q, true>(w[d], [&](int j) { return trow[2 << j]; });
   });
   const int nx = a.nx;
   const bool even_nx = (nx & 1) == 0;
@@ -358,10 +378,7 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
     }
     first_dft<P, -1>(v);
     const cx<T>* trow = tw_row(tw, S::L, unsigned(q));
-    static_for<1, P>([&](auto kk) {
-      constexpr int k1 = decltype(kk)::value;
-      v[k1] = cmul(v[k1], trow[k1]);
-    });
+    twiddle_run<P, false>(v, [&](int j) { return trow[1 << j]; });
   });
   const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {
@@ -408,10 +425,7 @@ __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, l
     const int k1 = tl + TL * d;
     dft<Q, +1>(w[d]);
     const cx<T>* trow = tw_row(tw, S::L, unsigned(k1));
-    static_for<1, Q>([&](auto nn) {
-      constexpr int n2 = decltype(nn)::value;
-      w[d][n2] = cmulc(w[d][n2], trow[n2]);
-    });
+    twiddle_run<Q, true>(w[d], [&](int j) { return trow[1 << j]; });
   });
   const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {

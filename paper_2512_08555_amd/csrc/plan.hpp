@@ -32,10 +32,18 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);
 ups_status set_error(ups_status s, const char* msg);
+// A second stream (default priority) and two events: the remainder launch of
+// a split column pass runs beside the main launch (fork on `fork`, join on
+// `join`).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
-                         const void* f, void* u, void* work, hipStream_t st);
+                         const void* f, void* u, void* work, hipStream_t st, const SideStream* side);
 int default_slab(const PlanGeom& g);
-void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st);
+void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
+                     const SideStream* side = nullptr);
 int slab_count(const PlanGeom& g, int slab);
 PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* work, void** wslab);
 
@@ -51,4 +59,6 @@ struct ups_plan_s {
   bool ready = false;
   int slab = 0;              // kx columns per y/z/y slab (0: one slab)
   ups::PassArgs args{};
+  ups::SideStream side;
+  ~ups_plan_s();
 };

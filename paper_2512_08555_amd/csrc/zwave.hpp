@@ -70,30 +70,6 @@ constexpr int zwave_slot() {
 
 __device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
 
-// v[k] *= w^(k x) (conjugated if CONJ) for k = 1 .. K-1, given pw(j) =
-// w^(2^j x): the other powers are products of earlier ones (k = 2^j + r,
-// w^(k x) = w^(2^j x) w^(r x)), so a run of K - 1 twiddles costs log2 K
-// table loads.
-template <int K, bool CONJ, typename T, typename PW>
-__device__ __forceinline__ void twiddle_run(cx<T>* v, PW pw) {
-  static_assert((K & (K - 1)) == 0, "power-of-two run length");
-  cx<T> p[K];
-  static_for<1, K>([&](auto kk) {
-    constexpr int k = decltype(kk)::value;
-    constexpr int hb = 1 << (31 - __builtin_clz(k));   // largest power of two <= k
-    if constexpr (hb == k) {
-      p[k] = pw(31 - __builtin_clz(k));
-    } else {
-      p[k] = cmul(p[hb], p[k - hb]);
-    }
-    v[k] = CONJ ? cmulc(v[k], p[k]) : cmul(v[k], p[k]);
-  });
-}
-
-// Move the E values of every lane through the slot xf (T[]), real parts
-// first: value i of this lane is stored at xf[waddr(i)] and value i
-// afterwards is loaded from xf[raddr(i)].  All lanes of the wave take part;
-// LDS accesses of one wave complete in order, so no barrier is needed.
 template <typename T, int E, typename WA, typename RA>
 __device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA raddr) {
   T o[E];
