@@ -166,6 +166,15 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
 ups_status ups_plan_set_slab(ups_plan_t plan, int columns);
 int ups_plan_slab(ups_plan_t plan);
 
+/* Each column pass runs over the largest multiple of 8 x (columns per
+ * 128-byte line) x-frequencies in one launch and over the remaining columns
+ * in a second, narrower launch.  With `enable` != 0 the second launch runs
+ * on a plan-owned stream, forked from and joined back into the caller's
+ * stream with events; 0 (the default: measured no faster at 512^3) puts it
+ * on the caller's stream after the first.  Results are identical either
+ * way. */
+ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);
+
 /* Enqueue one pass of the solve on the bound work buffer W, for testing and
  * per-kernel timing: pass 0 reads the real array `in` and writes W; passes
  * 1-3 update W in place (in/out ignored); pass 4 reads W and writes the real

@@ -60,6 +60,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_longlong), C.POINTER(C.c_size_t), C.POINTER(C.c_longlong)]),
     "ups_plan_set_slab": (C.c_int, [C.c_void_p, C.c_int]),
     "ups_plan_slab": (C.c_int, [C.c_void_p]),
+    "ups_plan_set_side_stream": (C.c_int, [C.c_void_p, C.c_int]),
     "ups_plan_model_bytes": (C.c_double, [C.c_void_p, C.c_int]),
     "ups_plan_destroy": (C.c_int, [C.c_void_p]),
     "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),

@@ -396,7 +396,7 @@ ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   ups_status s = check_io(plan, f, u);
   if (s != UPS_OK) return s;
   s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->work, static_cast<hipStream_t>(stream),
-                    &plan->side);
+                    plan->use_side ? &plan->side : nullptr);
   return s == UPS_OK ? ok() : s;
 }
 
@@ -412,7 +412,8 @@ ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, vo
   ups_status s = check_io(plan, i, o);
   if (s != UPS_OK) return s;
   if (pass >= 1 && pass <= 3)
-    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream), &plan->side);
+    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream),
+                    plan->use_side ? &plan->side : nullptr);
   else
     plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();
@@ -467,6 +468,12 @@ ups_status ups_plan_set_slab(ups_plan_t plan, int columns) {
 }
 
 int ups_plan_slab(ups_plan_t plan) { return plan ? plan->slab : -1; }
+
+ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  plan->use_side = enable != 0;
+  return ok();
+}
 
 double ups_plan_model_bytes(ups_plan_t plan, int pass) {
   if (!plan || pass < -1 || pass > 4) return 0.0;

@@ -25,7 +25,7 @@ std::vector<PassVariant> variants_f32_pow2() {
       YF(float, 16, 32, 2, 1), YI(float, 16, 32, 2, 1),
       YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
       YF(float, 32, 32, 8, 1), YF(float, 32, 32, 4, 1), YF(float, 32, 32, 4, 2),
-      ZW(float, 16, 8), ZWG(float, 16, 8), ZW(float, 16, 4), ZWG(float, 16, 4), ZW(float, 16, 1),
+      ZW(float, 16, 8), ZWO(float, 16, 8), ZWG(float, 16, 8), ZW(float, 16, 4), ZWG(float, 16, 4), ZW(float, 16, 1),
       ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
       ZC(float, 32, 32, 8, 1), ZC(float, 32, 32, 4, 1), ZC(float, 32, 32, 4, 2),
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),

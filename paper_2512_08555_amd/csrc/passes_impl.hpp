@@ -349,7 +349,9 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
 // p < P/2 when P is even).  ubase = element 0 of the tile's first column,
 // elements of a line `stride` apart.  Leaves w[d3][k2] = X[k1 + P k2],
 // k1 = tl + TL d3.
-template <typename T, int P, int Q, int C, int NCH>
+// TWP: a thread's twiddle run from log2 table loads and products (fewer
+// loads, more VALU) instead of one table load per twiddle.
+template <typename T, int P, int Q, int C, int NCH, bool TWP>
 __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, int cload, int nlive,
                                             const cx<T>* tw, cx<T>* lds, int c, int tl,
                                             ColSpec<T, P, Q>& w) {
@@ -378,7 +380,14 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
     }
     first_dft<P, -1>(v);
     const cx<T>* trow = tw_row(tw, S::L, unsigned(q));
-    twiddle_run<P, false>(v, [&](int j) { return trow[1 << j]; });
+    if constexpr (TWP) {
+      twiddle_run<P, false>(v, [&](int j) { return trow[1 << j]; });
+    } else {
+      static_for<1, P>([&](auto kk) {
+        constexpr int k1 = decltype(kk)::value;
+        v[k1] = cmul(v[k1], trow[k1]);
+      });
+    }
   });
   const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {
@@ -413,7 +422,7 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
 // Inverse step: per thread w[d3][k2] = X[k1 + P k2] (k1 = tl + TL d3) in,
 // stores x[n2 + Q n1] for n1 < P/2 (n2 = tl + TL d1) where n < nkeep.
 // Starts with a barrier (the LDS may still be read by a previous phase).
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool TWP>
 __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, long long stride, bool valid,
                                             int nkeep, const cx<T>* tw, cx<T>* lds, int c, int tl) {
   using S = Split<P, Q>;
@@ -425,7 +434,14 @@ __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, l
     const int k1 = tl + TL * d;
     dft<Q, +1>(w[d]);
     const cx<T>* trow = tw_row(tw, S::L, unsigned(k1));
-    twiddle_run<Q, true>(w[d], [&](int j) { return trow[1 << j]; });
+    if constexpr (TWP) {
+      twiddle_run<Q, true>(w[d], [&](int j) { return trow[1 << j]; });
+    } else {
+      static_for<1, Q>([&](auto nn) {
+        constexpr int n2 = decltype(nn)::value;
+        w[d][n2] = cmulc(w[d][n2], trow[n2]);
+      });
+    }
   });
   const int cl = c % CG;
   static_for<0, NCH>([&](auto hh) {
@@ -564,7 +580,7 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, false>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
   if (valid) {
     static_for<0, S::D3>([&](auto dd) {
       constexpr int d = decltype(dd)::value;
@@ -604,7 +620,7 @@ __device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs&
       w[d][k2] = ld_at(ubase + (long long)(P * k2) * a.px, toff);
     });
   });
-  col_inverse<T, P, Q, C, NCH>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
+  col_inverse<T, P, Q, C, NCH, false>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
 }
 
 // Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
@@ -629,7 +645,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, true>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
@@ -644,7 +660,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
       w[d][k2] = scale(w[d][k2], g);
     });
   });
-  col_inverse<T, P, Q, C, NCH>(w, ubase, a.plane, valid, a.nz, tw, lds, c, tl);
+  col_inverse<T, P, Q, C, NCH, true>(w, ubase, a.plane, valid, a.nz, tw, lds, c, tl);
 }
 
 // ============================================================================

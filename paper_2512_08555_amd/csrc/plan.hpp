@@ -60,5 +60,6 @@ struct ups_plan_s {
   int slab = 0;              // kx columns per y/z/y slab (0: one slab)
   ups::PassArgs args{};
   ups::SideStream side;
+  bool use_side = false;     // remainder launches on the side stream
   ~ups_plan_s();
 };

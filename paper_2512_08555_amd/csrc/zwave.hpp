@@ -68,6 +68,19 @@ constexpr int zwave_slot() {
   return need;
 }
 
+// Twiddle rows staged in LDS once per workgroup (short lines: measured
+// faster at E = 8) or read from the table where used (E = 16: fewer registers).
+template <int E>
+constexpr bool zwave_lds_twiddles() { return E <= 8; }
+
+// LDS of one workgroup: CW column slots plus the staged twiddle rows.
+template <typename T, int E, int CW>
+constexpr int zwave_lds_bytes() {
+  constexpr int A = 64 / E;
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  return int(sizeof(cx<T>)) * (CW * zwave_slot<E, CW>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
+}
+
 __device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
 
 template <typename T, int E, typename WA, typename RA>
@@ -97,7 +110,15 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   constexpr int S1 = Z::S1, P2 = Z::P2, S4 = Z::S4;
   constexpr int CS = zwave_slot<E, CW>();
   constexpr unsigned CB = sizeof(cx<T>);
+  // every twiddle run reads rows 2^j of the 64 x 64 product table (run
+  // lengths E and A): the workgroup copies those rows into LDS once
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  constexpr bool LT = zwave_lds_twiddles<E>();
   __shared__ cx<T> tile[CW * CS];
+  __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
+  // row 2^j, column x of the product table, from LDS or from the table
+  auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, M, 1u << j)[x]; };
 
   const int ntiles = (a.kx + CW - 1) / CW;
   const ColMap mp = zmap(bx, ntiles, a.my, a.ncomp, col_slots<T, CW>(ntiles));
@@ -117,13 +138,23 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     const int iy = ky <= a.my - ky ? ky : a.my - ky;
     gline = static_cast<const T*>(a.ghat) + iy * a.g_plane + (long long)(kx0 + cg) * a.gz;
   }
+  // register i holds kz = lane + base(i), base(i) = 64 (i / A) + E^2 (i % A); a
+  // base below M/2 keeps the whole wave below M/2 (iz = kz, ascending), a base
+  // at or above M/2 keeps it above (iz = M - kz, descending): a constant
+  // offset from one of two per-lane pointers, no per-element index math
+  const T* gup = gline + lane;
+  const T* gdn = gline - lane;
   auto gload = [&](int i) {
-    const int kz = lane + 64 * (i / A) + E2 * (i % A);
-    return gline[kz <= M - kz ? kz : M - kz];
+    const int base = 64 * (i / A) + E2 * (i % A);
+    return base < M / 2 ? gup[base] : gdn[M - base];
   };
   T gpre[GP ? E : 1];
   if constexpr (GP) {
     static_for<0, E>([&](auto ii) { gpre[decltype(ii)::value] = gload(decltype(ii)::value); });
+  }
+
+  if constexpr (LT) {
+    for (int i = t; i < NR * 64; i += 64 * CW) twl[i] = tw_row(tw, M, 1u << (i / 64))[i % 64];
   }
 
   // ---- coalesced tile load: thread (tc, tr) moves rows tr + 64 i of column tc
@@ -156,7 +187,6 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   // ---- wave c: the line of column kx0 + c
   cx<T>* slot = tile + c * CS;
   T* xf = reinterpret_cast<T*>(slot);
-  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
   cx<T> v[E];
   static_for<0, E / 2>([&](auto jj) {
     constexpr int j = decltype(jj)::value;
@@ -164,7 +194,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   });
   // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
   dft_half_in<E, -1>(v);
-  twiddle_run<E, false>(v, [&](int j) { return tw_row(tw, M, 1u << j)[lane]; });
+  twiddle_run<E, false>(v, [&](int j) { return trow(j, lane); });
   // exchange 1: (l, k1) at k1 S1 + l; lane (k1, l1) reads l2 at k1 S1 + l1 + A l2
   {
     const int k1 = lane % E, l1 = lane / E;
@@ -175,7 +205,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   dft<E, -1>(v);
   {
     const int el1 = E * (lane / E);
-    twiddle_run<E, false>(v, [&](int j) { return tw_row(tw, M, 1u << j)[el1]; });
+    twiddle_run<E, false>(v, [&](int j) { return trow(j, el1); });
   }
   // exchange 2: (a = k1 + E m1, l1) at l1 P2 + a; lane L reads register
   // r A + l1 (a = L + 64 r)
@@ -202,7 +232,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     static_for<1, A>([&](auto nn) {
       constexpr int n0 = decltype(nn)::value;
       constexpr int hb = 1 << (31 - __builtin_clz(n0));
-      if constexpr (hb == n0) q[n0] = tw_row(tw, M, unsigned(n0))[lane];
+      if constexpr (hb == n0) q[n0] = trow(31 - __builtin_clz(n0), lane);
       else q[n0] = cmul(q[hb], q[n0 - hb]);
     });
     static_for<0, R3>([&](auto rr) {
@@ -225,7 +255,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   dft<E, +1>(v);
   {
     const int ab = A * (lane % E);
-    twiddle_run<E, true>(v, [&](int j) { return tw_row(tw, M, 1u << j)[ab]; });
+    twiddle_run<E, true>(v, [&](int j) { return trow(j, ab); });
   }
   // inverse exchange 2: (b, n0, e) at e S4 + E n0 + (b ^ swz(n0)); lane
   // (n0, e) = n0 + A e reads b
@@ -268,8 +298,11 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   }
 }
 
-template <typename T, int E, int CW, bool GP>
-__global__ void __launch_bounds__(64 * CW) k_zwave(cx<T>* __restrict__ W, PassArgs a) {
+// OCC: minimum waves per SIMD asked of the register allocator (1: no
+// constraint; 8 caps registers at 64, spilling a few values to scratch).
+template <typename T, int E, int CW, bool GP, int OCC>
+__global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(OCC)))
+k_zwave(cx<T>* __restrict__ W, PassArgs a) {
   zwave_body<T, E, CW, GP>(W, a, blockIdx.x);
 }
 template <typename T, int E, int CW, bool GP>
@@ -285,9 +318,9 @@ template <typename T, int CW>
 inline unsigned zwave_blocks(const PassArgs& a) {
   return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, col_slots<T, CW>(cdiv(a.kx, CW)));
 }
-template <typename T, int E, int CW, bool GP>
+template <typename T, int E, int CW, bool GP, int OCC = 1>
 void launch_zwave(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave<T, E, CW, GP>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_zwave<T, E, CW, GP, OCC>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
 template <typename T, int E, int CW, bool GP>
@@ -299,11 +332,15 @@ void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
 // wave-per-line family; the "_g" variants load G_hat at the start.
 #define ZW(T, E, CW)                                                                              \
   PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              int(sizeof(cx<T>)) * CW * zwave_slot<E, CW>(), "zconv_" #T "_w" #E "_c" #CW,        \
+              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW,        \
               &launch_zwave<T, E, CW, false>, &launchg_zwave<T, E, CW, false>}
+#define ZWO(T, E, CW)                                                                             \
+  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
+              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_o8",  \
+              &launch_zwave<T, E, CW, false, 8>, &launchg_zwave<T, E, CW, false>}
 #define ZWG(T, E, CW)                                                                             \
   PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              int(sizeof(cx<T>)) * CW * zwave_slot<E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_g",   \
+              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_g",   \
               &launch_zwave<T, E, CW, true>, &launchg_zwave<T, E, CW, true>}
 
 }  // namespace ups

@@ -144,6 +144,10 @@ class Plan:
     def slab(self, columns):
         capi.check(capi.lib().ups_plan_set_slab(self._h, int(columns)))
 
+    def set_side_stream(self, enable):
+        """Run the narrow remainder launches on a second stream (default) or not."""
+        capi.check(capi.lib().ups_plan_set_side_stream(self._h, int(bool(enable))))
+
     def model_bytes(self, k=-1):
         return capi.lib().ups_plan_model_bytes(self._h, int(k))
 
