@@ -58,8 +58,8 @@ def solve_full(f, h, M=None):
     _check_M(N, M)
     Gh = green_spectrum_raw(M)
     full = Gh[np.ix_(_mirror(M[0]), _mirror(M[1]), np.arange(M[2] // 2 + 1))]
-    fh = np.fft.rfftn(f, s=M)
-    u = np.fft.irfftn(fh * (float(h) ** 2 * full), s=M)
+    fh = np.fft.rfftn(f, s=M, axes=(0, 1, 2))
+    u = np.fft.irfftn(fh * (float(h) ** 2 * full), s=M, axes=(0, 1, 2))
     return u[: N[0], : N[1], : N[2]]
 
 
