@@ -12,7 +12,7 @@ std::vector<PassVariant> variants_f32_pow2() {
       X_VARIANTS(float, 8, 8, 16, 2),       // mx = 128
       X_VARIANTS(float, 8, 16, 16, 2),      // mx = 256
       X_VARIANTS(float, 16, 16, 16, 2),     // mx = 512
-      XF(float, 16, 32, 8, 2), XF(float, 16, 32, 4, 1), XF(float, 16, 32, 8, 1),   // mx = 1024
+      XF(float, 16, 32, 4, 1), XF(float, 16, 32, 8, 2), XF(float, 16, 32, 8, 1),   // mx = 1024
       XF(float, 32, 16, 8, 2), XF(float, 16, 32, 16, 2), XF(float, 16, 32, 16, 4),
       XI(float, 16, 32, 16, 4), XI(float, 16, 32, 4, 1), XI(float, 16, 32, 8, 1),
       XI(float, 32, 16, 8, 2), XI(float, 16, 32, 8, 2), XI(float, 16, 32, 16, 2),
@@ -20,12 +20,13 @@ std::vector<PassVariant> variants_f32_pow2() {
       COL_VARIANTS(float, 8, 8, 16, 1),     // 64
       COL_VARIANTS(float, 8, 16, 16, 2),    // 128
       COL_VARIANTS(float, 16, 16, 16, 2),   // 256
-      ZWG(float, 8, 8), ZW(float, 8, 8), ZW(float, 8, 4), ZW(float, 8, 1),   // 512
+      ZW(float, 8, 16), ZWG(float, 8, 8), ZW(float, 8, 8), ZW(float, 8, 4), ZW(float, 8, 1),   // 512
       COL_VARIANTS(float, 16, 32, 16, 2),
       YF(float, 16, 32, 2, 1), YI(float, 16, 32, 2, 1),
       YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
       YF(float, 32, 32, 8, 1), YF(float, 32, 32, 4, 1), YF(float, 32, 32, 4, 2),
-      ZW(float, 16, 8), ZWO(float, 16, 8), ZWG(float, 16, 8), ZW(float, 16, 4), ZWG(float, 16, 4), ZW(float, 16, 1),
+      ZW(float, 16, 16), ZW(float, 16, 8), ZWO(float, 16, 8), ZWG(float, 16, 8), ZW(float, 16, 4), ZWG(float, 16, 4),
+      ZW(float, 16, 1),
       ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
       ZC(float, 32, 32, 8, 1), ZC(float, 32, 32, 4, 1), ZC(float, 32, 32, 4, 2),
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),

@@ -47,14 +47,69 @@ using ColSpec = cx<T>[Split<P, Q>::D3][Q];
 
 // Loads and stores at a wave-uniform base plus a 32-bit per-thread byte
 // offset, so addresses need one vector register instead of a 64-bit pair.
-template <typename T>
+// NT: a nontemporal access (see the cache hints below).
+template <bool NT = false, typename T>
+__device__ __forceinline__ cx<T> ld_cx(const cx<T>* p) {
+  if constexpr (NT) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+    return cx<T>{v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+template <bool NT = false, typename T>
+__device__ __forceinline__ void st_cx(cx<T>* p, cx<T> v) {
+  if constexpr (NT) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<V2*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT = false, typename T>
+__device__ __forceinline__ T ld_r(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT = false, typename T>
+__device__ __forceinline__ void st_r(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <bool NT = false, typename T>
 __device__ __forceinline__ cx<T> ld_at(const cx<T>* ubase, unsigned byte_off) {
-  return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(ubase) + byte_off);
+  return ld_cx<NT>(reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(ubase) + byte_off));
 }
-template <typename T>
+template <bool NT = false, typename T>
 __device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) {
-  *reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(ubase) + byte_off) = v;
+  st_cx<NT>(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(ubase) + byte_off), v);
 }
+
+// Cache hints of the data sweeps.  Every pass reads its input and writes its
+// output once, so those lines need not stay in L2; a nontemporal load or
+// store says so, and leaves L2 to the twiddle rows and G_hat lines that
+// several workgroups share.  Whether that pays differs per pass (it changes
+// how reads and writes interleave at the memory controllers, and whether
+// the next pass finds recent lines still cached), so it is set per pass from
+// measurement: bit k of the load (store) mask marks pass k's data loads
+// (stores), k = 0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv; bit 5 of the load
+// mask marks the G_hat loads of the z pass.  Measured on MI355X at 512^3
+// (FP32 and FP64): nontemporal loads and stores in both forward passes
+// shorten them and the z pass after them; the same hints slow the z pass
+// itself and the inverse passes.
+#ifndef UPS_NT_LOAD_MASK
+#define UPS_NT_LOAD_MASK 0x03
+#endif
+#ifndef UPS_NT_STORE_MASK
+#define UPS_NT_STORE_MASK 0x03
+#endif
+constexpr int kNtGhatBit = 5;
+template <int K>
+constexpr bool nt_load() { return ((UPS_NT_LOAD_MASK) >> K) & 1; }
+template <int K>
+constexpr bool nt_store() { return ((UPS_NT_STORE_MASK) >> K) & 1; }
 // twiddle table entry exp(-2 pi i idx / M)
 template <typename T>
 __device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, unsigned idx) {
@@ -152,7 +207,7 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
     if (full) {
       static_for<0, live_in<P>()>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
-        v[d][p] = *reinterpret_cast<const cx<T>*>(src + 2 * (q + Q * p));
+        v[d][p] = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * (q + Q * p)));
       });
     } else {
       static_for<0, live_in<P>()>([&](auto pp) {
@@ -160,10 +215,10 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
         const int m = q + Q * p;  // packed index: reals 2m, 2m+1
         cx<T> val = zero_c<T>();
         if (even_nx) {
-          if (2 * m < nx) val = *reinterpret_cast<const cx<T>*>(src + 2 * m);
+          if (2 * m < nx) val = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * m));
         } else {
-          if (2 * m < nx) val.re = src[2 * m];
-          if (2 * m + 1 < nx) val.im = src[2 * m + 1];
+          if (2 * m < nx) val.re = ld_r<nt_load<0>()>(src + 2 * m);
+          if (2 * m + 1 < nx) val.im = ld_r<nt_load<0>()>(src + 2 * m + 1);
         }
         v[d][p] = val;
       });
@@ -227,7 +282,7 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
           // w_M^kk = w_M^tl w_M^(TL i) (kk = L: w_M^L = -i... as a constant)
           const cx<T> wk = i < L / TL ? twiddle_c<(long long)TL * i, 2 * L, -1>(wtl)
                                       : twiddle_c<(long long)L, 2 * L, -1>(cx<T>{T(1), T(0)});
-          dst[kk] = e + cmul(o, wk);
+          st_cx<nt_store<0>()>(dst + kk, e + cmul(o, wk));
         }
       });
     }
@@ -274,8 +329,8 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
       const int k = k1 + P * k2;
-      const cx<T> xk = src[k];
-      const cx<T> xm = conj(src[L - k]);
+      const cx<T> xk = ld_cx<nt_load<4>()>(src + k);
+      const cx<T> xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
       // conj w_M^k = conj w_M^k1 conj w_M^(P k2)
       w[d][k2] = (xk + xm) + mul_i<+1>(twiddle_c<(long long)P * k2, 2 * L, +1>(cmulc(xk - xm, wk1)));
     });
@@ -316,17 +371,17 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
           if (full) {
             static_for<0, live_in<P>()>([&](auto nn) {
               constexpr int n1 = decltype(nn)::value;
-              *reinterpret_cast<cx<T>*>(dst + 2 * (n2 + Q * n1)) = v[n1];
+              st_cx<nt_store<4>()>(reinterpret_cast<cx<T>*>(dst + 2 * (n2 + Q * n1)), v[n1]);
             });
           } else {
             static_for<0, live_in<P>()>([&](auto nn) {
               constexpr int n1 = decltype(nn)::value;
               const int m = n2 + Q * n1;
               if (even_nx) {
-                if (2 * m < nx) *reinterpret_cast<cx<T>*>(dst + 2 * m) = v[n1];
+                if (2 * m < nx) st_cx<nt_store<4>()>(reinterpret_cast<cx<T>*>(dst + 2 * m), v[n1]);
               } else {
-                if (2 * m < nx) dst[2 * m] = v[n1].re;
-                if (2 * m + 1 < nx) dst[2 * m + 1] = v[n1].im;
+                if (2 * m < nx) st_r<nt_store<4>()>(dst + 2 * m, v[n1].re);
+                if (2 * m + 1 < nx) st_r<nt_store<4>()>(dst + 2 * m + 1, v[n1].im);
               }
             });
           }
@@ -351,7 +406,7 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
 // k1 = tl + TL d3.
 // TWP: a thread's twiddle run from log2 table loads and products (fewer
 // loads, more VALU) instead of one table load per twiddle.
-template <typename T, int P, int Q, int C, int NCH, bool TWP>
+template <typename T, int P, int Q, int C, int NCH, bool TWP, bool NTL>
 __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, int cload, int nlive,
                                             const cx<T>* tw, cx<T>* lds, int c, int tl,
                                             ColSpec<T, P, Q>& w) {
@@ -370,12 +425,12 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
     if (nlive >= Q * live_in<P>()) {  // every loaded row is live (the zero-padded case)
       static_for<0, live_in<P>()>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
-        v[p] = ld_at(ubase + (long long)(Q * p) * stride, toff);
+        v[p] = ld_at<NTL>(ubase + (long long)(Q * p) * stride, toff);
       });
     } else {
       static_for<0, live_in<P>()>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
-        v[p] = q + Q * p < nlive ? ld_at(ubase + (long long)(Q * p) * stride, toff) : zero_c<T>();
+        v[p] = q + Q * p < nlive ? ld_at<NTL>(ubase + (long long)(Q * p) * stride, toff) : zero_c<T>();
       });
     }
     first_dft<P, -1>(v);
@@ -422,7 +477,7 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
 // Inverse step: per thread w[d3][k2] = X[k1 + P k2] (k1 = tl + TL d3) in,
 // stores x[n2 + Q n1] for n1 < P/2 (n2 = tl + TL d1) where n < nkeep.
 // Starts with a barrier (the LDS may still be read by a previous phase).
-template <typename T, int P, int Q, int C, int NCH, bool TWP>
+template <typename T, int P, int Q, int C, int NCH, bool TWP, bool NTS>
 __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, long long stride, bool valid,
                                             int nkeep, const cx<T>* tw, cx<T>* lds, int c, int tl) {
   using S = Split<P, Q>;
@@ -480,7 +535,7 @@ __device__ __forceinline__ void col_inverse(ColSpec<T, P, Q>& w, cx<T>* ubase, l
       static_for<0, live_in<P>()>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
         cx<T>* bp = ubase + (long long)(Q * n1) * stride;
-        if (n2 + Q * n1 < nkeep) st_at(bp, toff, v[n1]);
+        if (n2 + Q * n1 < nkeep) st_at<NTS>(bp, toff, v[n1]);
       });
     }
   });
@@ -580,7 +635,7 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH, false>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, false, nt_load<1>()>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
   if (valid) {
     static_for<0, S::D3>([&](auto dd) {
       constexpr int d = decltype(dd)::value;
@@ -588,7 +643,7 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
       const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(c)) * unsigned(sizeof(cx<T>));
       static_for<0, Q>([&](auto kk) {
         constexpr int k2 = decltype(kk)::value;
-        st_at(ubase + (long long)(P * k2) * a.px, toff, w[d][k2]);
+        st_at<nt_store<1>()>(ubase + (long long)(P * k2) * a.px, toff, w[d][k2]);
       });
     });
   }
@@ -617,10 +672,10 @@ __device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs&
     const unsigned toff = (unsigned(k1) * unsigned(a.px) + unsigned(cload)) * unsigned(sizeof(cx<T>));
     static_for<0, Q>([&](auto kk) {
       constexpr int k2 = decltype(kk)::value;
-      w[d][k2] = ld_at(ubase + (long long)(P * k2) * a.px, toff);
+      w[d][k2] = ld_at<nt_load<3>()>(ubase + (long long)(P * k2) * a.px, toff);
     });
   });
-  col_inverse<T, P, Q, C, NCH, false>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
+  col_inverse<T, P, Q, C, NCH, false, nt_store<3>()>(w, ubase, a.px, valid, a.ny, tw, lds, c, tl);
 }
 
 // Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
@@ -645,7 +700,7 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH, true>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, true, nt_load<2>()>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
@@ -656,11 +711,12 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
       const unsigned goff = (unsigned(c) * unsigned(a.gz) + unsigned(iz)) * unsigned(sizeof(T));
       // (the branch also keeps the scheduler from hoisting these loads,
       // which would hold 32 more registers through the forward transform)
-      const T g = valid ? *reinterpret_cast<const T*>(reinterpret_cast<const char*>(gbase) + goff) : T(0);
+      const T g = valid ? ld_r<nt_load<kNtGhatBit>()>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(gbase) + goff))
+                        : T(0);
       w[d][k2] = scale(w[d][k2], g);
     });
   });
-  col_inverse<T, P, Q, C, NCH, true>(w, ubase, a.plane, valid, a.nz, tw, lds, c, tl);
+  col_inverse<T, P, Q, C, NCH, true, nt_store<2>()>(w, ubase, a.plane, valid, a.nz, tw, lds, c, tl);
 }
 
 // ============================================================================

@@ -70,6 +70,8 @@ constexpr int zwave_slot() {
 
 // Twiddle rows staged in LDS once per workgroup (short lines: measured
 // faster at E = 8) or read from the table where used (E = 16: fewer registers).
+// (Loading every twiddle from the table instead of forming powers by
+// products takes about 30 more registers per lane and measured 30% slower.)
 template <int E>
 constexpr bool zwave_lds_twiddles() { return E <= 8; }
 
@@ -146,7 +148,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   const T* gdn = gline - lane;
   auto gload = [&](int i) {
     const int base = 64 * (i / A) + E2 * (i % A);
-    return base < M / 2 ? gup[base] : gdn[M - base];
+    return ld_r<nt_load<kNtGhatBit>()>(base < M / 2 ? gup + base : gdn + (M - base));
   };
   T gpre[GP ? E : 1];
   if constexpr (GP) {
@@ -167,7 +169,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     cx<T> ld[E / 2];
     static_for<0, E / 2>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
-      ld[i] = ld_at(ubase + (long long)(64 * i) * a.plane, toff);
+      ld[i] = ld_at<nt_load<2>()>(ubase + (long long)(64 * i) * a.plane, toff);
     });
     static_for<0, E / 2>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
@@ -178,7 +180,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
       constexpr int i = decltype(ii)::value;
       const int row = tr + 64 * i;
       const int rowc = row < nz ? row : nz - 1;  // clamped: loads stay in bounds
-      const cx<T> val = ld_at(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB);
+      const cx<T> val = ld_at<nt_load<2>()>(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB);
       tslot[row] = row < nz ? val : zero_c<T>();
     });
   }
@@ -284,7 +286,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     if (full) {
       static_for<0, E / 2>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        st_at(ubase + (long long)(64 * i) * a.plane, toff, tslot[tr + 64 * i]);
+        st_at<nt_store<2>()>(ubase + (long long)(64 * i) * a.plane, toff, tslot[tr + 64 * i]);
       });
     } else {
       // rows >= nz write row nz - 1 again (the same value): no per-row branch
@@ -292,7 +294,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
         constexpr int i = decltype(ii)::value;
         const int row = tr + 64 * i;
         const int rowc = row < nz ? row : nz - 1;
-        st_at(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB, tslot[rowc]);
+        st_at<nt_store<2>()>(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB, tslot[rowc]);
       });
     }
   }
@@ -329,18 +331,14 @@ void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
 }
 
 // P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
-// wave-per-line family; the "_g" variants load G_hat at the start.
-#define ZW(T, E, CW)                                                                              \
+// wave-per-line family; the "_g" variants load G_hat at the start, "_o8"
+// asks for 8 waves per SIMD.
+#define ZWV(T, E, CW, SUF, GP, OCC)                                                               \
   PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW,        \
-              &launch_zwave<T, E, CW, false>, &launchg_zwave<T, E, CW, false>}
-#define ZWO(T, E, CW)                                                                             \
-  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_o8",  \
-              &launch_zwave<T, E, CW, false, 8>, &launchg_zwave<T, E, CW, false>}
-#define ZWG(T, E, CW)                                                                             \
-  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW "_g",   \
-              &launch_zwave<T, E, CW, true>, &launchg_zwave<T, E, CW, true>}
+              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW SUF,                      \
+              &launch_zwave<T, E, CW, GP, OCC>, &launchg_zwave<T, E, CW, GP>}
+#define ZW(T, E, CW) ZWV(T, E, CW, "", false, 1)
+#define ZWO(T, E, CW) ZWV(T, E, CW, "_o8", false, 8)
+#define ZWG(T, E, CW) ZWV(T, E, CW, "_g", true, 1)
 
 }  // namespace ups
