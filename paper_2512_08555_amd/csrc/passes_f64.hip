@@ -1,7 +1,7 @@
 // Kernel instantiations: double, power-of-two padded lengths 32 .. 1024.
 // The first variant listed for a (pass, length) is the default (ordered by
 // measured time on MI355X for the 256^3 and 512^3 grids).
-#include "zwave.hpp"
+#include "ywave.hpp"
 
 namespace ups {
 
@@ -21,12 +21,14 @@ std::vector<PassVariant> variants_f64() {
       YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
       ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
       ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZWG(double, 8, 4), ZW(double, 8, 1),
+      YIW(double, 8, 8), YIW(double, 8, 4), YIW(double, 8, 1), YIWP(double, 8, 8),
       YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
       YF(double, 16, 32, 2, 1), YI(double, 16, 32, 2, 1),
       YF(double, 32, 32, 8, 4), YF(double, 32, 32, 8, 2),   // 1024
       ZW(double, 16, 8), ZWG(double, 16, 8), ZW(double, 16, 4), ZWG(double, 16, 4), ZW(double, 16, 1),
       ZW(double, 16, 16),
       ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
+      YIWP(double, 16, 8), YIW(double, 16, 8), YIW(double, 16, 4), YIW(double, 16, 1),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
       YF(double, 32, 32, 2, 1), YI(double, 32, 32, 2, 1),
   };

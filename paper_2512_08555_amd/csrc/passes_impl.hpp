@@ -95,17 +95,20 @@ __device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) 
 // the next pass finds recent lines still cached), so it is set per pass from
 // measurement: bit k of the load (store) mask marks pass k's data loads
 // (stores), k = 0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv; bit 5 of the load
-// mask marks the G_hat loads of the z pass.  Measured on MI355X at 512^3
-// (FP32 and FP64): nontemporal loads and stores in both forward passes
-// shorten them and the z pass after them; the same hints slow the z pass
-// itself and the inverse passes.
+// mask marks the G_hat loads of the z pass, bit 6 the wave-per-line kernels
+// of pass 4 (bit 3 then covers its column kernels).  Measured on MI355X at
+// 512^3 (FP32 and FP64): nontemporal loads and stores in both forward passes
+// shorten them and the z pass after them, and nontemporal stores shorten
+// the wave-per-line pass 4 and the x pass after it; every other hint slows
+// the pass it is in or the one after.
 #ifndef UPS_NT_LOAD_MASK
 #define UPS_NT_LOAD_MASK 0x03
 #endif
 #ifndef UPS_NT_STORE_MASK
-#define UPS_NT_STORE_MASK 0x03
+#define UPS_NT_STORE_MASK 0x43
 #endif
 constexpr int kNtGhatBit = 5;
+constexpr int kNtYinvWaveBit = 6;
 template <int K>
 constexpr bool nt_load() { return ((UPS_NT_LOAD_MASK) >> K) & 1; }
 template <int K>

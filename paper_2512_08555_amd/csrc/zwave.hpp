@@ -103,13 +103,106 @@ __device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA
   wave_fence();
 }
 
+// Forward transform of one line held by a wave: on entry v[j] (j < E/2)
+// holds row lane + 64 j (rows M/2 .. M-1 are the zero padding); on exit
+// register r A + m2 holds X[lane + 64 r + E^2 m2].  xf: the wave's LDS
+// exchange area; trow(j, x) = w_M^(2^j x).
+template <typename T, int E, typename TR>
+__device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR trow) {
+  using Z = ZWave<E>;
+  constexpr int A = Z::A, R3 = Z::R3, S1 = Z::S1, P2 = Z::P2;
+  // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
+  dft_half_in<E, -1>(v);
+  twiddle_run<E, false>(v, [&](int j) { return trow(j, lane); });
+  // exchange 1: (l, k1) at k1 S1 + l; lane (k1, l1) reads l2 at k1 S1 + l1 + A l2
+  {
+    const int k1 = lane % E, l1 = lane / E;
+    const int rb = k1 * S1 + l1;
+    wave_exchange<T, E>(v, xf, [&](int i) { return lane + i * S1; }, [&](int i) { return rb + A * i; });
+  }
+  // stage 2: DFT_E over l2, times w_64^(l1 m1) = T[E l1][m1]
+  dft<E, -1>(v);
+  {
+    const int el1 = E * (lane / E);
+    twiddle_run<E, false>(v, [&](int j) { return trow(j, el1); });
+  }
+  // exchange 2: (a = k1 + E m1, l1) at l1 P2 + a; lane L reads register
+  // r A + l1 (a = L + 64 r)
+  {
+    const int wb = (lane / E) * P2 + lane % E;
+    wave_exchange<T, E>(v, xf, [&](int i) { return wb + E * i; },
+                        [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); });
+  }
+  // stage 3: lane L, register r A + m2 holds k = L + 64 r + E^2 m2
+  static_for<0, R3>([&](auto rr) {
+    constexpr int r = decltype(rr)::value;
+    dft<A, -1>(&v[r * A]);
+  });
+}
+
+// Inverse transform, first half of the outputs: on entry register r A + m2
+// holds X[lane + 64 r + E^2 m2] (the layout zw_forward leaves); on exit v[f]
+// (f < E/2) holds the unnormalised inverse DFT at row lane + 64 f.
+template <typename T, int E, typename TR>
+__device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR trow) {
+  using Z = ZWave<E>;
+  constexpr int M = Z::M, A = Z::A, R3 = Z::R3, P2 = Z::P2, S4 = Z::S4;
+  // inverse stage A: DFT_A over m2, times conj w_M^(n0 a), a = L + 64 r:
+  // w_M^(n0 L) = T[n0][L] and the constant w_M^(64 n0 r)
+  {
+    // w_M^(n0 L) for n0 < A, shared by the R3 groups
+    cx<T> q[A];
+    static_for<1, A>([&](auto nn) {
+      constexpr int n0 = decltype(nn)::value;
+      constexpr int hb = 1 << (31 - __builtin_clz(n0));
+      if constexpr (hb == n0) q[n0] = trow(31 - __builtin_clz(n0), lane);
+      else q[n0] = cmul(q[hb], q[n0 - hb]);
+    });
+    static_for<0, R3>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      dft<A, +1>(&v[r * A]);
+      static_for<1, A>([&](auto nn) {
+        constexpr int n0 = decltype(nn)::value;
+        v[r * A + n0] = twiddle_c<(long long)64 * r * n0, M, +1>(cmulc(v[r * A + n0], q[n0]));
+      });
+    });
+  }
+  // inverse exchange 1: (a, n0) at n0 P2 + a; lane (b, n0) reads c at
+  // n0 P2 + b + E c
+  {
+    const int rb = (lane / E) * P2 + lane % E;
+    wave_exchange<T, E>(v, xf, [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); },
+                        [&](int i) { return rb + E * i; });
+  }
+  // inverse stage B: DFT_E over c, times conj w_M^(A e b) = T[A e][b]
+  dft<E, +1>(v);
+  {
+    const int ab = A * (lane % E);
+    twiddle_run<E, true>(v, [&](int j) { return trow(j, ab); });
+  }
+  // inverse exchange 2: (b, n0, e) at e S4 + E n0 + (b ^ swz(n0)); lane
+  // (n0, e) = n0 + A e reads b
+  {
+    constexpr int HE = E / 2;
+    const int b = lane % E, n0 = lane / E;
+    const int wb = E * n0 + (b ^ (n0 >= A / 2 ? HE : 0));
+    const int n0r = lane % A, er = lane / A;
+    const int sw = n0r >= A / 2 ? HE : 0;
+    const int rlo = er * S4 + E * n0r + sw;   // b < E/2: b ^ sw = b + sw
+    const int rhi = er * S4 + E * n0r - sw;   // b >= E/2: b ^ sw = b - sw
+    wave_exchange<T, E>(v, xf, [&](int i) { return wb + S4 * i; },
+                        [&](int i) { return (i < HE ? rlo : rhi) + i; });
+  }
+  // inverse stage C: rows lane + 64 f, f < E/2
+  dft_half_out<E, +1>(v);
+}
+
 // GP: load this lane's G_hat values at the start (they then share the
 // latency of the tile loads) instead of after the forward transform.
 template <typename T, int E, int CW, bool GP>
 __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
-  constexpr int M = Z::M, A = Z::A, E2 = Z::E2, R3 = Z::R3;
-  constexpr int S1 = Z::S1, P2 = Z::P2, S4 = Z::S4;
+  constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
   constexpr int CS = zwave_slot<E, CW>();
   constexpr unsigned CB = sizeof(cx<T>);
   // every twiddle run reads rows 2^j of the 64 x 64 product table (run
@@ -194,86 +287,14 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     constexpr int j = decltype(jj)::value;
     v[j] = slot[lane + 64 * j];
   });
-  // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
-  dft_half_in<E, -1>(v);
-  twiddle_run<E, false>(v, [&](int j) { return trow(j, lane); });
-  // exchange 1: (l, k1) at k1 S1 + l; lane (k1, l1) reads l2 at k1 S1 + l1 + A l2
-  {
-    const int k1 = lane % E, l1 = lane / E;
-    const int rb = k1 * S1 + l1;
-    wave_exchange<T, E>(v, xf, [&](int i) { return lane + i * S1; }, [&](int i) { return rb + A * i; });
-  }
-  // stage 2: DFT_E over l2, times w_64^(l1 m1) = T[E l1][m1]
-  dft<E, -1>(v);
-  {
-    const int el1 = E * (lane / E);
-    twiddle_run<E, false>(v, [&](int j) { return trow(j, el1); });
-  }
-  // exchange 2: (a = k1 + E m1, l1) at l1 P2 + a; lane L reads register
-  // r A + l1 (a = L + 64 r)
-  {
-    const int wb = (lane / E) * P2 + lane % E;
-    wave_exchange<T, E>(v, xf, [&](int i) { return wb + E * i; },
-                        [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); });
-  }
-  // stage 3 and G_hat: lane L, register r A + m2 holds kz = L + 64 r + E^2 m2
-  static_for<0, R3>([&](auto rr) {
-    constexpr int r = decltype(rr)::value;
-    dft<A, -1>(&v[r * A]);
-  });
+  zw_forward<T, E>(v, xf, lane, trow);
+  // G_hat: lane L, register r A + m2 holds kz = L + 64 r + E^2 m2
   static_for<0, E>([&](auto ii) {
     constexpr int i = decltype(ii)::value;
     if constexpr (GP) v[i] = scale(v[i], gpre[i]);
     else v[i] = scale(v[i], gload(i));
   });
-  // inverse stage A: DFT_A over m2, times conj w_M^(n0 a), a = L + 64 r:
-  // w_M^(n0 L) = T[n0][L] and the constant w_M^(64 n0 r)
-  {
-    // w_M^(n0 L) for n0 < A, shared by the R3 groups
-    cx<T> q[A];
-    static_for<1, A>([&](auto nn) {
-      constexpr int n0 = decltype(nn)::value;
-      constexpr int hb = 1 << (31 - __builtin_clz(n0));
-      if constexpr (hb == n0) q[n0] = trow(31 - __builtin_clz(n0), lane);
-      else q[n0] = cmul(q[hb], q[n0 - hb]);
-    });
-    static_for<0, R3>([&](auto rr) {
-      constexpr int r = decltype(rr)::value;
-      dft<A, +1>(&v[r * A]);
-      static_for<1, A>([&](auto nn) {
-        constexpr int n0 = decltype(nn)::value;
-        v[r * A + n0] = twiddle_c<(long long)64 * r * n0, M, +1>(cmulc(v[r * A + n0], q[n0]));
-      });
-    });
-  }
-  // inverse exchange 1: (a, n0) at n0 P2 + a; lane (b, n0) reads c at
-  // n0 P2 + b + E c
-  {
-    const int rb = (lane / E) * P2 + lane % E;
-    wave_exchange<T, E>(v, xf, [&](int i) { return lane + (i % A) * P2 + 64 * (i / A); },
-                        [&](int i) { return rb + E * i; });
-  }
-  // inverse stage B: DFT_E over c, times conj w_M^(A e b) = T[A e][b]
-  dft<E, +1>(v);
-  {
-    const int ab = A * (lane % E);
-    twiddle_run<E, true>(v, [&](int j) { return trow(j, ab); });
-  }
-  // inverse exchange 2: (b, n0, e) at e S4 + E n0 + (b ^ swz(n0)); lane
-  // (n0, e) = n0 + A e reads b
-  {
-    constexpr int HE = E / 2;
-    const int b = lane % E, n0 = lane / E;
-    const int wb = E * n0 + (b ^ (n0 >= A / 2 ? HE : 0));
-    const int n0r = lane % A, er = lane / A;
-    const int sw = n0r >= A / 2 ? HE : 0;
-    const int rlo = er * S4 + E * n0r + sw;   // b < E/2: b ^ sw = b + sw
-    const int rhi = er * S4 + E * n0r - sw;   // b >= E/2: b ^ sw = b - sw
-    wave_exchange<T, E>(v, xf, [&](int i) { return wb + S4 * i; },
-                        [&](int i) { return (i < HE ? rlo : rhi) + i; });
-  }
-  // inverse stage C, rows lane + 64 f (f < E/2) back into the slot
-  dft_half_out<E, +1>(v);
+  zw_inverse<T, E>(v, xf, lane, trow);
   wave_fence();
   static_for<0, E / 2>([&](auto ff) {
     constexpr int f = decltype(ff)::value;

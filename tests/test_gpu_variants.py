@@ -64,35 +64,39 @@ def test_variant_matches_oracle(prec, M, k, name, ragged):
     assert err < tol, (name, err)
 
 
-def _zwave_cases():
+def _wave_cases():
     out = []
     for prec, lengths in (("f32", (512, 1024)), ("f64", (512, 1024))):
         for M in lengths:
-            for nm in kernel_variants(2, prec, M):
-                if "_w" in nm:
-                    out.append((prec, M, nm))
+            for k in (2, 3):
+                for nm in kernel_variants(k, prec, M):
+                    if "_w" in nm:
+                        out.append((k, prec, M, nm))
     return out
 
 
 try:
-    ZW_CASES = _zwave_cases()
+    WAVE_CASES = _wave_cases()
 except Exception:  # library not built: collection must still work
-    ZW_CASES = []
+    WAVE_CASES = []
 
 
-@pytest.mark.parametrize("prec,M,name", ZW_CASES)
-def test_zpass_aligned_columns_plus_remainder(prec, M, name):
-    """257 x-frequencies: the z pass runs 256 aligned columns and one left
-    over through the narrow kernel."""
-    shape, pad = (M // 2 - 3, 6, 140), (M, 32, 512)
-    print("[case] z split %s M %d %s" % (name, M, prec), flush=True)
-    rng = np.random.default_rng(M)
+@pytest.mark.parametrize("k,prec,M,name", WAVE_CASES)
+def test_wave_pass_aligned_columns_plus_remainder(k, prec, M, name):
+    """257 x-frequencies: a wave-per-line pass runs 256 aligned columns and
+    one left over through the narrow kernel of its family."""
+    ax = AXIS_OF_PASS[k]
+    shape, pad = [6, 6, 140], [32, 32, 512]
+    shape[ax], pad[ax] = M // 2 - 3, M
+    shape, pad = tuple(shape), tuple(pad)
+    print("[case] column split %s pass %d M %d %s" % (name, k, M, prec), flush=True)
+    rng = np.random.default_rng(M + k)
     f = rng.standard_normal(shape)
     if prec == "f32":
         f = f.astype(np.float32).astype(np.float64)
     h = 1.0 / 512
     plan = Plan(shape, h, prec, pad=pad)
-    plan.set_kernel(2, name)
+    plan.set_kernel(k, name)
     dt = torch.float64 if prec == "f64" else torch.float32
     u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
     ref = oracle.solve(f, h, M=pad)
