@@ -26,7 +26,7 @@ std::vector<PassVariant> variants_f64() {
       YF(double, 16, 32, 2, 1), YI(double, 16, 32, 2, 1),
       YF(double, 32, 32, 8, 4), YF(double, 32, 32, 8, 2),   // 1024
       ZW(double, 16, 8), ZWG(double, 16, 8), ZW(double, 16, 4), ZWG(double, 16, 4), ZW(double, 16, 1),
-      ZW(double, 16, 16),
+      ZW(double, 16, 16), ZWT(double, 16, 4),
       ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
       YIWP(double, 16, 8), YIW(double, 16, 8), YIW(double, 16, 4), YIW(double, 16, 1),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),

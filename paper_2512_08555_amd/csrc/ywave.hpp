@@ -15,8 +15,9 @@
 namespace ups {
 
 // PRE: issue the loads of both halves at the start (the second half waits
-// in registers while the first is read out of LDS).
-template <typename T, int E, int CW, bool PRE>
+// in registers while the first is read out of LDS).  TB: twiddles of the
+// inverse stages A and B from LDS tables.
+template <typename T, int E, int CW, bool PRE, bool TB>
 __device__ __forceinline__ void ywinv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
@@ -27,6 +28,7 @@ __device__ __forceinline__ void ywinv_body(cx<T>* __restrict__ W, const PassArgs
   constexpr bool LT = zwave_lds_twiddles<E>();
   __shared__ cx<T> tile[CW * CS];
   __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  __shared__ cx<T> ztab[TB ? ZTab<E>::total : 1];
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   // row 2^j, column x of the product table, from LDS or from the table
   auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, M, 1u << j)[x]; };
@@ -44,6 +46,7 @@ __device__ __forceinline__ void ywinv_body(cx<T>* __restrict__ W, const PassArgs
   if constexpr (LT) {
     for (int i = t; i < NR * 64; i += 64 * CW) twl[i] = tw_row(tw, M, 1u << (i / 64))[i % 64];
   }
+  if constexpr (TB) zw_fill_tables<T, E>(ztab, tw, t, 64 * CW);
 
   // tile rows: thread (tc, tr) moves rows tr + 64 i of column tc
   const int tc = t % CW, tr = t / CW;
@@ -82,7 +85,7 @@ __device__ __forceinline__ void ywinv_body(cx<T>* __restrict__ W, const PassArgs
       if constexpr (base / H2 == h) v[i] = slot[lane + base - H2 * h];
     });
   });
-  zw_inverse<T, E>(v, xf, lane, trow);
+  zw_inverse<T, E, TB>(v, xf, lane, trow, ztab);
   wave_fence();
   static_for<0, E / 2>([&](auto ff) {
     constexpr int f = decltype(ff)::value;
@@ -109,35 +112,37 @@ __device__ __forceinline__ void ywinv_body(cx<T>* __restrict__ W, const PassArgs
   }
 }
 
-template <typename T, int E, int CW, bool PRE>
+template <typename T, int E, int CW, bool PRE, bool TB>
 __global__ void __launch_bounds__(64 * CW) k_ywinv(cx<T>* __restrict__ W, PassArgs a) {
-  ywinv_body<T, E, CW, PRE>(W, a, blockIdx.x);
+  ywinv_body<T, E, CW, PRE, TB>(W, a, blockIdx.x);
 }
-template <typename T, int E, int CW, bool PRE>
+template <typename T, int E, int CW, bool PRE, bool TB>
 __global__ void __launch_bounds__(64 * CW) k_ywinv_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  ywinv_body<T, E, CW, PRE>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  ywinv_body<T, E, CW, PRE, TB>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
-template <typename T, int E, int CW, bool PRE>
+template <typename T, int E, int CW, bool PRE, bool TB>
 void launch_ywinv(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_ywinv<T, E, CW, PRE>), dim3(ypass_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_ywinv<T, E, CW, PRE, TB>), dim3(ypass_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int CW, bool PRE>
+template <typename T, int E, int CW, bool PRE, bool TB>
 void launchg_ywinv(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_ywinv_g<T, E, CW, PRE>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+  hipLaunchKernelGGL((k_ywinv_g<T, E, CW, PRE, TB>), dim3(nblocks), dim3(64 * CW), 0, s, g);
 }
 
 // P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
-// wave-per-line family; "_p" variants issue all their loads at the start.
-#define YIWV(T, E, CW, SUF, PRE)                                                                  \
-  PassVariant{PASS_YINV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW, zwave_lds_bytes<T, E, CW>(),   \
-              "yinv_" #T "_w" #E "_c" #CW SUF, &launch_ywinv<T, E, CW, PRE>,                      \
-              &launchg_ywinv<T, E, CW, PRE>}
-#define YIW(T, E, CW) YIWV(T, E, CW, "", false)
-#define YIWP(T, E, CW) YIWV(T, E, CW, "_p", true)
+// wave-per-line family; "_p" variants issue all their loads at the start,
+// "_t" variants take the inverse twiddles from LDS tables.
+#define YIWV(T, E, CW, SUF, PRE, TB)                                                              \
+  PassVariant{PASS_YINV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW, zwave_lds_bytes<T, E, CW, TB>(), \
+              "yinv_" #T "_w" #E "_c" #CW SUF, &launch_ywinv<T, E, CW, PRE, TB>,                  \
+              &launchg_ywinv<T, E, CW, PRE, TB>}
+#define YIW(T, E, CW) YIWV(T, E, CW, "", false, false)
+#define YIWP(T, E, CW) YIWV(T, E, CW, "_p", true, false)
+#define YIWT(T, E, CW) YIWV(T, E, CW, "_pt", true, true)
 
 }  // namespace ups

@@ -57,6 +57,23 @@ struct ZWave {
   static constexpr int xfloats = cmax(cmax(E * S1, A * P2), (E - 1) * S4 + 64);
 };
 
+// Twiddles of the later stages from tables in LDS, built once per workgroup
+// from the length-M table (tw[m] = w_M^m):
+//   t2[l1 (E+1) + m1]       = w_M^(E l1 m1),  l1 < A, m1 < E   (stage 2)
+//   ta[(n0-1) (M/A) + a]    = w_M^(n0 a),     n0 < A, a < M/A  (inverse stage A)
+//   tb[b (E+1) + e]         = w_M^(A e b),    b, e < E         (inverse stage B)
+// Rows of E+1 entries put the lane groups that read different rows of t2
+// and tb in different banks.  One load per twiddle instead of products.
+// Table loads are issued in groups of kTabGroup between compiler fences, so
+// that the compiler does not hoist all of a stage's loads (and their
+// registers) ahead of the arithmetic.
+constexpr int kTabGroup = 2;
+template <int E>
+struct ZTab {
+  static constexpr int M = 64 * E, A = 64 / E;
+  static constexpr int n2 = A * (E + 1), na = (A - 1) * (M / A), nb = E * (E + 1);
+  static constexpr int o2 = 0, oa = n2, ob = n2 + na, total = n2 + na + nb;
+};
 // Complex elements per LDS column slot: room for the nz <= M/2 tile rows and
 // for one exchange (floats), with slot stride = 16 / CW (mod 16) so that the
 // 64-bit tile accesses of the CW columns fall in different banks.
@@ -75,12 +92,14 @@ constexpr int zwave_slot() {
 template <int E>
 constexpr bool zwave_lds_twiddles() { return E <= 8; }
 
-// LDS of one workgroup: CW column slots plus the staged twiddle rows.
-template <typename T, int E, int CW>
+// LDS of one workgroup: CW column slots plus the staged twiddle rows, plus
+// the later-stage twiddle tables if TB.
+template <typename T, int E, int CW, bool TB = false>
 constexpr int zwave_lds_bytes() {
   constexpr int A = 64 / E;
   constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
-  return int(sizeof(cx<T>)) * (CW * zwave_slot<E, CW>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
+  return int(sizeof(cx<T>)) * (CW * zwave_slot<E, CW>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1) +
+                               (TB ? ZTab<E>::total : 1));
 }
 
 __device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
@@ -103,12 +122,34 @@ __device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA
   wave_fence();
 }
 
+template <typename T, int E>
+__device__ __forceinline__ void zw_fill_tables(cx<T>* tab, const cx<T>* tw, int t, int nthreads) {
+  using Z = ZTab<E>;
+  constexpr int M = Z::M, A = Z::A;
+  for (int i = t; i < Z::total; i += nthreads) {
+    int e;
+    if (i < Z::oa) {
+      const int l1 = i / (E + 1), m1 = i % (E + 1);
+      e = (E * l1 * m1) % M;
+    } else if (i < Z::ob) {
+      const int j = i - Z::oa;
+      e = (j / (M / A) + 1) * (j % (M / A));  // n0 a < M
+    } else {
+      const int j = i - Z::ob;
+      e = (A * (j / (E + 1)) * (j % (E + 1))) % M;
+    }
+    tab[i] = tw_at(tw, unsigned(e));
+  }
+}
+
 // Forward transform of one line held by a wave: on entry v[j] (j < E/2)
 // holds row lane + 64 j (rows M/2 .. M-1 are the zero padding); on exit
 // register r A + m2 holds X[lane + 64 r + E^2 m2].  xf: the wave's LDS
 // exchange area; trow(j, x) = w_M^(2^j x).
-template <typename T, int E, typename TR>
-__device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR trow) {
+// TB: stage-2 twiddles from the ZTab tables at tab (LDS), else by products
+// of table rows.
+template <typename T, int E, bool TB, typename TR>
+__device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR trow, const cx<T>* tab) {
   using Z = ZWave<E>;
   constexpr int A = Z::A, R3 = Z::R3, S1 = Z::S1, P2 = Z::P2;
   // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
@@ -122,7 +163,14 @@ __device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR tr
   }
   // stage 2: DFT_E over l2, times w_64^(l1 m1) = T[E l1][m1]
   dft<E, -1>(v);
-  {
+  if constexpr (TB) {
+    const cx<T>* r2 = tab + ZTab<E>::o2 + (E + 1) * (lane / E);
+    static_for<1, E>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if constexpr (k % kTabGroup == 0) wave_fence();  // loads stay near their use
+      v[k] = cmul(v[k], r2[k]);
+    });
+  } else {
     const int el1 = E * (lane / E);
     twiddle_run<E, false>(v, [&](int j) { return trow(j, el1); });
   }
@@ -143,13 +191,26 @@ __device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR tr
 // Inverse transform, first half of the outputs: on entry register r A + m2
 // holds X[lane + 64 r + E^2 m2] (the layout zw_forward leaves); on exit v[f]
 // (f < E/2) holds the unnormalised inverse DFT at row lane + 64 f.
-template <typename T, int E, typename TR>
-__device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR trow) {
+// TB: twiddles of stages A and B from the ZTab tables at tab (LDS), else
+// from table rows and products.
+template <typename T, int E, bool TB, typename TR>
+__device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR trow, const cx<T>* tab) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, R3 = Z::R3, P2 = Z::P2, S4 = Z::S4;
   // inverse stage A: DFT_A over m2, times conj w_M^(n0 a), a = L + 64 r:
   // w_M^(n0 L) = T[n0][L] and the constant w_M^(64 n0 r)
-  {
+  if constexpr (TB) {
+    const cx<T>* ra = tab + ZTab<E>::oa + lane;
+    static_for<0, R3>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      dft<A, +1>(&v[r * A]);
+      static_for<1, A>([&](auto nn) {
+        constexpr int n0 = decltype(nn)::value;
+        if constexpr ((r * A + n0) % kTabGroup == 0) wave_fence();
+        v[r * A + n0] = cmulc(v[r * A + n0], ra[(n0 - 1) * (M / A) + 64 * r]);
+      });
+    });
+  } else {
     // w_M^(n0 L) for n0 < A, shared by the R3 groups
     cx<T> q[A];
     static_for<1, A>([&](auto nn) {
@@ -176,7 +237,14 @@ __device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR tr
   }
   // inverse stage B: DFT_E over c, times conj w_M^(A e b) = T[A e][b]
   dft<E, +1>(v);
-  {
+  if constexpr (TB) {
+    const cx<T>* rb = tab + ZTab<E>::ob + (E + 1) * (lane % E);
+    static_for<1, E>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if constexpr (k % kTabGroup == 0) wave_fence();
+      v[k] = cmulc(v[k], rb[k]);
+    });
+  } else {
     const int ab = A * (lane % E);
     twiddle_run<E, true>(v, [&](int j) { return trow(j, ab); });
   }
@@ -199,7 +267,8 @@ __device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR tr
 
 // GP: load this lane's G_hat values at the start (they then share the
 // latency of the tile loads) instead of after the forward transform.
-template <typename T, int E, int CW, bool GP>
+// TB: twiddles of stage 2 and of the inverse stages A and B from LDS tables.
+template <typename T, int E, int CW, bool GP, bool TB>
 __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
@@ -211,6 +280,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   constexpr bool LT = zwave_lds_twiddles<E>();
   __shared__ cx<T> tile[CW * CS];
   __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  __shared__ cx<T> ztab[TB ? ZTab<E>::total : 1];
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
   // row 2^j, column x of the product table, from LDS or from the table
   auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, M, 1u << j)[x]; };
@@ -251,6 +321,7 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
   if constexpr (LT) {
     for (int i = t; i < NR * 64; i += 64 * CW) twl[i] = tw_row(tw, M, 1u << (i / 64))[i % 64];
   }
+  if constexpr (TB) zw_fill_tables<T, E>(ztab, tw, t, 64 * CW);
 
   // ---- coalesced tile load: thread (tc, tr) moves rows tr + 64 i of column tc
   const int tc = t % CW, tr = t / CW;
@@ -287,14 +358,14 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     constexpr int j = decltype(jj)::value;
     v[j] = slot[lane + 64 * j];
   });
-  zw_forward<T, E>(v, xf, lane, trow);
+  zw_forward<T, E, TB>(v, xf, lane, trow, ztab);
   // G_hat: lane L, register r A + m2 holds kz = L + 64 r + E^2 m2
   static_for<0, E>([&](auto ii) {
     constexpr int i = decltype(ii)::value;
     if constexpr (GP) v[i] = scale(v[i], gpre[i]);
     else v[i] = scale(v[i], gload(i));
   });
-  zw_inverse<T, E>(v, xf, lane, trow);
+  zw_inverse<T, E, TB>(v, xf, lane, trow, ztab);
   wave_fence();
   static_for<0, E / 2>([&](auto ff) {
     constexpr int f = decltype(ff)::value;
@@ -323,43 +394,44 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
 
 // OCC: minimum waves per SIMD asked of the register allocator (1: no
 // constraint; 8 caps registers at 64, spilling a few values to scratch).
-template <typename T, int E, int CW, bool GP, int OCC>
+template <typename T, int E, int CW, bool GP, int OCC, bool TB>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_zwave(cx<T>* __restrict__ W, PassArgs a) {
-  zwave_body<T, E, CW, GP>(W, a, blockIdx.x);
+  zwave_body<T, E, CW, GP, TB>(W, a, blockIdx.x);
 }
-template <typename T, int E, int CW, bool GP>
+template <typename T, int E, int CW, bool GP, bool TB>
 __global__ void __launch_bounds__(64 * CW) k_zwave_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  zwave_body<T, E, CW, GP>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  zwave_body<T, E, CW, GP, TB>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 
 template <typename T, int CW>
 inline unsigned zwave_blocks(const PassArgs& a) {
   return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, col_slots<T, CW>(cdiv(a.kx, CW)));
 }
-template <typename T, int E, int CW, bool GP, int OCC = 1>
+template <typename T, int E, int CW, bool GP, int OCC, bool TB>
 void launch_zwave(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave<T, E, CW, GP, OCC>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_zwave<T, E, CW, GP, OCC, TB>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int CW, bool GP>
+template <typename T, int E, int CW, bool GP, bool TB>
 void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave_g<T, E, CW, GP>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+  hipLaunchKernelGGL((k_zwave_g<T, E, CW, GP, TB>), dim3(nblocks), dim3(64 * CW), 0, s, g);
 }
 
 // P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
 // wave-per-line family; the "_g" variants load G_hat at the start, "_o8"
-// asks for 8 waves per SIMD.
-#define ZWV(T, E, CW, SUF, GP, OCC)                                                               \
+// asks for 8 waves per SIMD, "_t" takes the later twiddles from LDS tables.
+#define ZWV(T, E, CW, SUF, GP, OCC, TB)                                                           \
   PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
-              zwave_lds_bytes<T, E, CW>(), "zconv_" #T "_w" #E "_c" #CW SUF,                      \
-              &launch_zwave<T, E, CW, GP, OCC>, &launchg_zwave<T, E, CW, GP>}
-#define ZW(T, E, CW) ZWV(T, E, CW, "", false, 1)
-#define ZWO(T, E, CW) ZWV(T, E, CW, "_o8", false, 8)
-#define ZWG(T, E, CW) ZWV(T, E, CW, "_g", true, 1)
+              zwave_lds_bytes<T, E, CW, TB>(), "zconv_" #T "_w" #E "_c" #CW SUF,                  \
+              &launch_zwave<T, E, CW, GP, OCC, TB>, &launchg_zwave<T, E, CW, GP, TB>}
+#define ZW(T, E, CW) ZWV(T, E, CW, "", false, 1, false)
+#define ZWO(T, E, CW) ZWV(T, E, CW, "_o8", false, 8, false)
+#define ZWG(T, E, CW) ZWV(T, E, CW, "_g", true, 1, false)
+#define ZWT(T, E, CW) ZWV(T, E, CW, "_t", false, 1, true)
 
 }  // namespace ups
