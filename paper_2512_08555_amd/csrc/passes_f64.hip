@@ -1,6 +1,7 @@
 // Kernel instantiations: double, power-of-two padded lengths 32 .. 1024.
 // The first variant listed for a (pass, length) is the default (ordered by
 // measured time on MI355X for the 256^3 and 512^3 grids).
+#include "xwave.hpp"
 #include "ywave.hpp"
 
 namespace ups {
@@ -12,6 +13,7 @@ std::vector<PassVariant> variants_f64() {
       X_VARIANTS(double, 8, 8, 8, 2),
       X_VARIANTS(double, 8, 16, 8, 2),
       X_VARIANTS(double, 16, 16, 8, 2),
+      XFW(double, 8, 8), XFW(double, 8, 4), XIW(double, 8, 8), XIW(double, 8, 4),   // mx = 1024
       XF(double, 16, 32, 8, 2), XF(double, 16, 32, 8, 4),
       XI(double, 16, 32, 8, 2), XI(double, 16, 32, 8, 4),
       COL_VARIANTS(double, 4, 8, 8, 1),

@@ -1,0 +1,237 @@
+// Pass 5 with one wavefront per row: complex-to-real untangle of the half
+// spectrum X[0..L] (L = mx/2 = 64 E), inverse DFT of length L on the wave,
+// keep x < nx.
+//
+//   Z[k] = (X[k] + conj X[L-k]) + i conj(w_2L^k) (X[k] - conj X[L-k]),  k < L,
+//
+// and the inverse DFT of Z gives u[2m] + i u[2m+1] (unnormalised).  Lane l,
+// register r A + m2 loads k = l + 64 r + E^2 m2 straight from the row (both
+// X[k] and X[L-k] are contiguous across the wave), which is the layout the
+// inverse stages of the z pass take; those stages leave output pair
+// m = l + 64 f (f < E/2) in register f, and only m < L/2 is kept (nx <= L).
+// No staging and no barrier: the row is contiguous in W.
+//
+// Pass 1 the same way: the real row packed as z[m] = f[2m] + i f[2m+1]
+// (m < nx/2 <= L/2, the zero padding is the upper half), the forward stages
+// of the z pass, then the untangle
+//
+//   X[k] = (Z[k] + conj Z[L-k])/2 - i w_2L^k (Z[k] - conj Z[L-k])/2,  k <= L
+//
+// with Z[L-k] read back from the wave's LDS area (the whole Z goes there).
+#pragma once
+#include "zwave.hpp"
+
+namespace ups {
+
+template <typename T, int E, int RW>
+__device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __restrict__ u, const PassArgs& a,
+                                           unsigned bx, unsigned by) {
+  using Z = ZWave<E>;
+  constexpr int L = Z::M, A = Z::A, E2 = Z::E2;
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  constexpr bool LT = zwave_lds_twiddles<E>();
+  constexpr int XS = (Z::xfloats + 1) / 2;  // complex elements of one wave's exchange area
+  __shared__ cx<T> xs[RW * XS];
+  __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);  // table of length 2L
+  // w_L^(2^j x) = w_2L^(2^(j+1) x): row 2^(j+1) of the x table's product block
+  auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, 2 * L, 2u << j)[x]; };
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  if constexpr (LT) {
+    for (int i = t; i < NR * 64; i += 64 * RW) twl[i] = tw_row(tw, 2 * L, 2u << (i / 64))[i % 64];
+    __syncthreads();
+  }
+  const long long row = (long long)bx * RW + wv;
+  if (row >= (long long)a.ny * a.nz) return;  // no barrier below
+  const int comp = int(by);
+  const int y = int(row % a.ny), z = int(row / a.ny);
+  const cx<T>* src = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
+  T* dst = u + comp * a.comp_f + row * a.nx;
+  T* xf = reinterpret_cast<T*>(xs + wv * XS);
+
+  // untangle; conj w_2L^k = conj w_2L^lane * conj w_2L^base
+  const cx<T> wl = tw_at(tw, unsigned(lane));
+  cx<T> v[E];
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    constexpr int base = 64 * (i / A) + E2 * (i % A);
+    const int k = lane + base;  // k < L, so L - k is in 1 .. L
+    const cx<T> xk = ld_cx<nt_load<4>()>(src + k);
+    const cx<T> xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
+    v[i] = (xk + xm) + mul_i<+1>(twiddle_c<base, 2 * L, +1>(cmulc(xk - xm, wl)));
+  });
+  zw_inverse<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+
+  const int nx = a.nx;
+  if (nx == L) {  // every pair m < L/2 is inside the row
+    static_for<0, E / 2>([&](auto ff) {
+      constexpr int f = decltype(ff)::value;
+      st_cx<nt_store<4>()>(reinterpret_cast<cx<T>*>(dst + 2 * (lane + 64 * f)), v[f]);
+    });
+  } else {
+    static_for<0, E / 2>([&](auto ff) {
+      constexpr int f = decltype(ff)::value;
+      const int m = lane + 64 * f;
+      if (2 * m < nx) st_r<nt_store<4>()>(dst + 2 * m, v[f].re);
+      if (2 * m + 1 < nx) st_r<nt_store<4>()>(dst + 2 * m + 1, v[f].im);
+    });
+  }
+}
+
+// LDS area of one wave in the forward x pass: the exchanges, or the whole
+// spectrum Z (L complex) for the untangle.
+template <int E>
+constexpr int xwfwd_slot() {
+  constexpr int a = (ZWave<E>::xfloats + 1) / 2, b = 64 * E;
+  return a > b ? a : b;
+}
+
+template <typename T, int E, int RW>
+__device__ __forceinline__ void xwfwd_body(const T* __restrict__ f, cx<T>* __restrict__ W, const PassArgs& a,
+                                           unsigned bx, unsigned by) {
+  using Z = ZWave<E>;
+  constexpr int L = Z::M, A = Z::A, E2 = Z::E2;
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  constexpr bool LT = zwave_lds_twiddles<E>();
+  constexpr int XS = xwfwd_slot<E>();
+  __shared__ cx<T> xs[RW * XS];
+  __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);  // table of length 2L
+  auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, 2 * L, 2u << j)[x]; };
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  if constexpr (LT) {
+    for (int i = t; i < NR * 64; i += 64 * RW) twl[i] = tw_row(tw, 2 * L, 2u << (i / 64))[i % 64];
+    __syncthreads();
+  }
+  const long long row = (long long)bx * RW + wv;
+  if (row >= (long long)a.ny * a.nz) return;  // no barrier below
+  const int comp = int(by);
+  const int y = int(row % a.ny), z = int(row / a.ny);
+  const T* src = f + comp * a.comp_f + row * a.nx;
+  cx<T>* dst = W + comp * a.comp_w + z * a.plane + (long long)y * a.px;
+  cx<T>* zs = xs + wv * XS;
+  T* xf = reinterpret_cast<T*>(zs);
+
+  // packed row: register j < E/2 takes m = lane + 64 j
+  const int nx = a.nx;
+  cx<T> v[E];
+  if (nx == L) {
+    static_for<0, E / 2>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      v[j] = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * (lane + 64 * j)));
+    });
+  } else {
+    const bool even_nx = (nx & 1) == 0;
+    static_for<0, E / 2>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int m = lane + 64 * j;
+      cx<T> val = zero_c<T>();
+      if (even_nx) {
+        if (2 * m < nx) val = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * m));
+      } else {
+        if (2 * m < nx) val.re = ld_r<nt_load<0>()>(src + 2 * m);
+        if (2 * m + 1 < nx) val.im = ld_r<nt_load<0>()>(src + 2 * m + 1);
+      }
+      v[j] = val;
+    });
+  }
+  zw_forward<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+  // register i holds Z[k], k = lane + base(i); the whole Z into LDS at k
+  wave_fence();
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    zs[lane + 64 * (i / A) + E2 * (i % A)] = v[i];
+  });
+  wave_fence();
+  const cx<T> wl = tw_at(tw, unsigned(lane));  // w_2L^lane
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    constexpr int base = 64 * (i / A) + E2 * (i % A);
+    const int k = lane + base;
+    const cx<T> zk = v[i];
+    const cx<T> zm = conj(zs[k == 0 ? 0 : L - k]);
+    const cx<T> e = scale(zk + zm, T(0.5));
+    const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));
+    st_cx<nt_store<0>()>(dst + k, e + cmul(o, twiddle_c<base, 2 * L, -1>(wl)));
+  });
+  if (lane == 0) {  // k = L: Z[L] = Z[0], w_2L^L = -1
+    const cx<T> z0 = zs[0];
+    st_cx<nt_store<0>()>(dst + L, cx<T>{z0.re - z0.im, T(0)});
+  }
+}
+
+template <typename T, int E, int RW>
+__global__ void __launch_bounds__(64 * RW) k_xwfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
+  xwfwd_body<T, E, RW>(f, W, a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int E, int RW>
+__global__ void __launch_bounds__(64 * RW) k_xwfwd_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
+  xwfwd_body<T, E, RW>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)), e.a,
+                       lin % gx, lin / gx);
+}
+template <typename T, int E, int RW>
+void launch_xwfwd(const PassArgs& a, const void* in, void* out, hipStream_t s) {
+  dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
+  hipLaunchKernelGGL((k_xwfwd<T, E, RW>), grid, dim3(64 * RW), 0, s, static_cast<const T*>(in),
+                     static_cast<cx<T>*>(out), a);
+}
+template <typename T, int E, int RW>
+void launchg_xwfwd(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_xwfwd_g<T, E, RW>), dim3(nblocks), dim3(64 * RW), 0, s, g);
+}
+
+template <typename T, int E, int RW>
+__global__ void __launch_bounds__(64 * RW) k_xwinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
+  xwinv_body<T, E, RW>(W, u, a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int E, int RW>
+__global__ void __launch_bounds__(64 * RW) k_xwinv_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
+  xwinv_body<T, E, RW>(static_cast<const cx<T>*>(group_in(g, e)), static_cast<T*>(group_out(g, e)), e.a,
+                       lin % gx, lin / gx);
+}
+template <typename T, int E, int RW>
+void launch_xwinv(const PassArgs& a, const void* in, void* out, hipStream_t s) {
+  dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
+  hipLaunchKernelGGL((k_xwinv<T, E, RW>), grid, dim3(64 * RW), 0, s, static_cast<const cx<T>*>(in),
+                     static_cast<T*>(out), a);
+}
+template <typename T, int E, int RW>
+void launchg_xwinv(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_xwinv_g<T, E, RW>), dim3(nblocks), dim3(64 * RW), 0, s, g);
+}
+template <typename T, int E, int RW>
+constexpr int xwfwd_lds_bytes() {
+  constexpr int A = 64 / E;
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  return int(sizeof(cx<T>)) * (RW * xwfwd_slot<E>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
+}
+template <typename T, int E, int RW>
+constexpr int xwave_lds_bytes() {
+  constexpr int A = 64 / E;
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  return int(sizeof(cx<T>)) * (RW * ((ZWave<E>::xfloats + 1) / 2) + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
+}
+
+// mx = 128 E; P = E, Q = 64 (half length 64 E), tile = RW rows (one wave
+// each), nch = 0 marks the wave-per-line family.
+#define XFW(T, E, RW)                                                                             \
+  PassVariant{PASS_XFWD, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW,                               \
+              xwfwd_lds_bytes<T, E, RW>(),                                                        \
+              "xfwd_" #T "_w" #E "_r" #RW, &launch_xwfwd<T, E, RW>, &launchg_xwfwd<T, E, RW>}
+#define XIW(T, E, RW)                                                                             \
+  PassVariant{PASS_XINV, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW, xwave_lds_bytes<T, E, RW>(),   \
+              "xinv_" #T "_w" #E "_r" #RW, &launch_xwinv<T, E, RW>, &launchg_xwinv<T, E, RW>}
+
+}  // namespace ups
