@@ -27,14 +27,15 @@ std::vector<PassVariant> variants_f32_pow2() {
       COL_VARIANTS(float, 16, 32, 16, 2),
       YF(float, 16, 32, 2, 1), YI(float, 16, 32, 2, 1),
       YIW(float, 8, 16), YIW(float, 8, 8), YIW(float, 8, 1), YIWP(float, 8, 8),
-      YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
+      YFW(float, 8, 16), YFW(float, 8, 8), YFW(float, 8, 1),
+      YFW(float, 16, 16), YF(float, 32, 32, 16, 2), YF(float, 32, 32, 16, 4), YF(float, 32, 32, 8, 2),   // 1024
       YF(float, 32, 32, 8, 1), YF(float, 32, 32, 4, 1), YF(float, 32, 32, 4, 2),
       ZWT(float, 16, 16), ZW(float, 16, 16), ZW(float, 16, 8), ZWO(float, 16, 8), ZWG(float, 16, 8), ZW(float, 16, 4), ZWG(float, 16, 4),
       ZW(float, 16, 1), ZWT(float, 16, 8),
       ZC(float, 32, 32, 8, 2), ZC(float, 32, 32, 16, 2), ZC(float, 32, 32, 16, 4),
       ZC(float, 32, 32, 8, 1), ZC(float, 32, 32, 4, 1), ZC(float, 32, 32, 4, 2),
       YIWP(float, 16, 16), YIW(float, 16, 16), YIW(float, 16, 8), YIW(float, 16, 1), YIWP(float, 16, 8),
-      YIWT(float, 16, 16),
+      YIWT(float, 16, 16), YFW(float, 16, 8), YFW(float, 16, 1),
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),
       YI(float, 32, 32, 16, 4), YI(float, 32, 32, 4, 1), YI(float, 32, 32, 4, 2),
       YF(float, 32, 32, 2, 1), YI(float, 32, 32, 2, 1),

@@ -21,16 +21,18 @@ std::vector<PassVariant> variants_f64() {
       COL_VARIANTS(double, 8, 16, 8, 2),
       COL_VARIANTS(double, 16, 16, 8, 2),
       YF(double, 16, 32, 8, 2), YF(double, 16, 32, 8, 4),   // 512
+      ZWG(double, 8, 4), ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZW(double, 8, 1),
       ZC(double, 16, 32, 8, 2), ZC(double, 16, 32, 8, 4),
-      ZW(double, 8, 8), ZWG(double, 8, 8), ZW(double, 8, 4), ZWG(double, 8, 4), ZW(double, 8, 1),
       YIW(double, 8, 8), YIW(double, 8, 4), YIW(double, 8, 1), YIWP(double, 8, 8),
+      YFW(double, 8, 8), YFW(double, 8, 4), YFW(double, 8, 1),
       YI(double, 16, 32, 8, 4), YI(double, 16, 32, 8, 2),
       YF(double, 16, 32, 2, 1), YI(double, 16, 32, 2, 1),
-      YF(double, 32, 32, 8, 4), YF(double, 32, 32, 8, 2),   // 1024
+      YFW(double, 16, 8), YF(double, 32, 32, 8, 4), YF(double, 32, 32, 8, 2),   // 1024
       ZW(double, 16, 8), ZWG(double, 16, 8), ZW(double, 16, 4), ZWG(double, 16, 4), ZW(double, 16, 1),
       ZW(double, 16, 16), ZWT(double, 16, 4),
       ZC(double, 32, 32, 8, 2), ZC(double, 32, 32, 8, 4),
       YIWP(double, 16, 8), YIW(double, 16, 8), YIW(double, 16, 4), YIW(double, 16, 1),
+      YFW(double, 16, 4), YFW(double, 16, 1),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
       YF(double, 32, 32, 2, 1), YI(double, 32, 32, 2, 1),
   };

@@ -9,10 +9,122 @@
 // loads, rows of CW columns); after each half every wave reads the rows of
 // its column that fall in that half straight into those registers.  The
 // kept rows go back through the column slot to coalesced stores.
+//
+// Pass 2 the same way: the tile's ny <= M/2 input rows come into LDS, each
+// wave takes rows lane + 64 j of its column (the forward stages' input
+// layout), runs the forward stages of the z pass, and the M output rows
+// leave through the column slots in two halves of M/2 rows.
 #pragma once
 #include "zwave.hpp"
 
 namespace ups {
+
+template <typename T, int E, int CW>
+__device__ __forceinline__ void ywfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
+  using Z = ZWave<E>;
+  constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
+  constexpr int H2 = M / 2;
+  constexpr int CS = zwave_slot<E, CW>();
+  constexpr unsigned CB = sizeof(cx<T>);
+  constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
+  constexpr bool LT = zwave_lds_twiddles<E>();
+  __shared__ cx<T> tile[CW * CS];
+  __shared__ cx<T> twl[LT ? NR * 64 : 1];
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
+  auto trow = [&](int j, int x) { return LT ? twl[64 * j + x] : tw_row(tw, M, 1u << j)[x]; };
+
+  const int ntiles = (a.kx + CW - 1) / CW;
+  const ColMap mp = ymap(bx, ntiles, a.nz, a.ncomp, col_slots<T, CW>(ntiles));
+  if (!mp.active) return;  // uniform over the workgroup, before any barrier
+  const int t = threadIdx.x;
+  const int lane = t & 63, c = t >> 6;
+  const int kx0 = mp.tile * CW;
+  cx<T>* ubase = W + mp.comp * a.comp_w + mp.line * a.plane + kx0;
+  const int ny = a.ny;
+
+  if constexpr (LT) {
+    for (int i = t; i < NR * 64; i += 64 * CW) twl[i] = tw_row(tw, M, 1u << (i / 64))[i % 64];
+  }
+
+  // tile rows: thread (tc, tr) moves rows tr + 64 i of column tc
+  const int tc = t % CW, tr = t / CW;
+  const bool tvalid = kx0 + tc < a.kx;
+  const int tcl = tvalid ? tc : a.kx - 1 - kx0;  // in-bounds column for the loads
+  const unsigned toff = (unsigned(tr) * unsigned(a.px) + unsigned(tcl)) * CB;
+  cx<T>* tslot = tile + tc * CS;
+  if (ny == H2) {
+    cx<T> ld[E / 2];
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      ld[i] = ld_at<nt_load<1>()>(ubase + (long long)(64 * i) * a.px, toff);
+    });
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      tslot[tr + 64 * i] = ld[i];
+    });
+  } else {
+    static_for<0, E / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const int row = tr + 64 * i;
+      const int rowc = row < ny ? row : ny - 1;  // clamped: loads stay in bounds
+      const cx<T> val = ld_at<nt_load<1>()>(ubase, (unsigned(rowc) * unsigned(a.px) + unsigned(tcl)) * CB);
+      tslot[row] = row < ny ? val : zero_c<T>();
+    });
+  }
+  __syncthreads();
+
+  cx<T>* slot = tile + c * CS;
+  T* xf = reinterpret_cast<T*>(slot);
+  cx<T> v[E];
+  static_for<0, E / 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    v[j] = slot[lane + 64 * j];
+  });
+  zw_forward<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+  // output rows k = lane + base(i) (base a multiple of 64: a wave's rows lie
+  // in one half), half h through the slots
+  static_for<0, 2>([&](auto hh) {
+    constexpr int h = decltype(hh)::value;
+    __syncthreads();  // h = 0: every wave is past its input reads; h = 1: the first half is stored
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      constexpr int base = 64 * (i / A) + E2 * (i % A);
+      if constexpr (base / H2 == h) slot[lane + base - H2 * h] = v[i];
+    });
+    __syncthreads();
+    if (tvalid) {
+      static_for<0, E / 2>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        st_at<nt_store<1>()>(ubase + (long long)(H2 * h + 64 * i) * a.px, toff, tslot[tr + 64 * i]);
+      });
+    }
+  });
+}
+
+template <typename T, int E, int CW>
+__global__ void __launch_bounds__(64 * CW) k_ywfwd(cx<T>* __restrict__ W, PassArgs a) {
+  ywfwd_body<T, E, CW>(W, a, blockIdx.x);
+}
+template <typename T, int E, int CW>
+__global__ void __launch_bounds__(64 * CW) k_ywfwd_g(GroupArgs g) {
+  unsigned lin;
+  bool live;
+  const GroupEntry& e = group_entry(g, &lin, &live);
+  if (!live) return;  // uniform over the workgroup, before any barrier
+  ywfwd_body<T, E, CW>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+}
+template <typename T, int E, int CW>
+void launch_ywfwd(const PassArgs& a, const void*, void* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_ywfwd<T, E, CW>), dim3(ypass_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+                     static_cast<cx<T>*>(out), a);
+}
+template <typename T, int E, int CW>
+void launchg_ywfwd(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_ywfwd_g<T, E, CW>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+}
+#define YFW(T, E, CW)                                                                             \
+  PassVariant{PASS_YFWD, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW, zwave_lds_bytes<T, E, CW>(),   \
+              "yfwd_" #T "_w" #E "_c" #CW, &launch_ywfwd<T, E, CW>, &launchg_ywfwd<T, E, CW>}
 
 // PRE: issue the loads of both halves at the start (the second half waits
 // in registers while the first is read out of LDS).  TB: twiddles of the
