@@ -121,6 +121,48 @@ __device__ __forceinline__ cx<T> twiddle_c(cx<T> z) {
   }
 }
 
+// Class of the constant exp(DIR 2 pi i E / R): 0 one, 1 a multiple of pi/2
+// other than 0 (a swap and sign flips), 2 an odd multiple of pi/4, 3 general.
+template <long long E, long long R>
+constexpr int twiddle_class() {
+  constexpr long long e = ((E % R) + R) % R;
+  if constexpr (e == 0) return 0;
+  else if constexpr ((4 * e) % R == 0) return 1;
+  else if constexpr ((8 * e) % R == 0) return 2;
+  else return 3;
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// u + z exp(DIR 2 pi i E / R) with the product folded into fused
+// multiply-adds: 4 operations for a general or pi/4-odd constant, instead
+// of 4 (twiddle) + 2 (add).
+template <long long E, long long R, int DIR, typename T>
+__device__ __forceinline__ cx<T> cmadd_c(cx<T> u, cx<T> z) {
+  constexpr int cls = twiddle_class<E, R>();
+  if constexpr (cls < 2) {
+    return u + twiddle_c<E, R, DIR>(z);
+  } else if constexpr (cls == 2) {
+    constexpr long long e = ((E % R) + R) % R;
+    constexpr int o = int((8 * e) / R);
+    constexpr int od = DIR > 0 ? o : (8 - o) % 8;  // angle = od * pi/4, od odd
+    constexpr T h = T(0.70710678118654752440084436210484903928);
+    if constexpr (od == 1) return {fma_t(h, z.re - z.im, u.re), fma_t(h, z.re + z.im, u.im)};
+    else if constexpr (od == 3) return {fma_t(-h, z.re + z.im, u.re), fma_t(h, z.re - z.im, u.im)};
+    else if constexpr (od == 5) return {fma_t(h, z.im - z.re, u.re), fma_t(-h, z.re + z.im, u.im)};
+    else return {fma_t(h, z.re + z.im, u.re), fma_t(h, z.im - z.re, u.im)};
+  } else {
+    constexpr cs_pair w = unit_root(DIR * (((E % R) + R) % R), R);
+    constexpr T c = T(w.c), sn = T(w.s);
+    return {fma_t(c, z.re, fma_t(-sn, z.im, u.re)),
+            fma_t(sn, z.re, fma_t(c, z.im, u.im))};
+  }
+}
+
 // ---- compile-time loops -----------------------------------------------------
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {

@@ -81,6 +81,20 @@ __device__ __forceinline__ void butterfly(cx<T>* y) {
   }
 }
 
+// a = x + w z, b = x - w z for the constant w = exp(DIR 2 pi i E / R): by
+// fused multiply-adds and b = 2 x - a when w is not trivial.
+template <long long E, long long R, int DIR, typename T>
+__device__ __forceinline__ void pm_pair(cx<T> x, cx<T> z, cx<T>& a, cx<T>& b) {
+  if constexpr (twiddle_class<E, R>() < 2) {
+    const cx<T> y = twiddle_c<E, R, DIR>(z);
+    a = x + y;
+    b = x - y;
+  } else {
+    a = cmadd_c<E, R, DIR>(x, z);
+    b = cx<T>{fma_t(T(2), x.re, -a.re), fma_t(T(2), x.im, -a.im)};
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* v) {
   static_assert(is_smooth7<R>(), "DFT length must be 7-smooth");
@@ -100,16 +114,36 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     });
     static_for<0, m>([&](auto kk) {
       constexpr int k = decltype(kk)::value;
-      cx<T> y[r];
-      static_for<0, r>([&](auto ss) {
-        constexpr int s = decltype(ss)::value;
-        y[s] = twiddle_c<(long long)s * k, R, DIR>(sub[s][k]);
-      });
-      butterfly<r, DIR>(y);
-      static_for<0, r>([&](auto tt) {
-        constexpr int t = decltype(tt)::value;
-        v[k + m * t] = y[t];
-      });
+      if constexpr (r == 4) {
+        // radix-4 combine; a pair x +- w x' whose w is not trivial is formed
+        // as a = x + w x' by fused multiply-adds and b = 2 x - a
+        const cx<T> x0 = sub[0][k];
+        const cx<T> t1 = twiddle_c<(long long)k, R, DIR>(sub[1][k]);
+        cx<T> a, b, c, d;
+        pm_pair<(long long)2 * k, R, DIR>(x0, sub[2][k], a, b);
+        pm_pair<(long long)3 * k, R, DIR>(t1, sub[3][k], c, d);
+        const cx<T> e = mul_i<DIR>(d);
+        v[k] = a + c;
+        v[k + m] = b + e;
+        v[k + 2 * m] = a - c;
+        v[k + 3 * m] = b - e;
+      } else if constexpr (r == 2) {
+        cx<T> a, b;
+        pm_pair<(long long)k, R, DIR>(sub[0][k], sub[1][k], a, b);
+        v[k] = a;
+        v[k + m] = b;
+      } else {
+        cx<T> y[r];
+        static_for<0, r>([&](auto ss) {
+          constexpr int s = decltype(ss)::value;
+          y[s] = twiddle_c<(long long)s * k, R, DIR>(sub[s][k]);
+        });
+        butterfly<r, DIR>(y);
+        static_for<0, r>([&](auto tt) {
+          constexpr int t = decltype(tt)::value;
+          v[k + m * t] = y[t];
+        });
+      }
     });
   }
 }
@@ -154,7 +188,7 @@ __device__ __forceinline__ void dft_half_out(cx<T>* v) {
   dft<H, DIR>(o);
   static_for<0, H>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
-    v[k] = e[k] + twiddle_c<k, R, DIR>(o[k]);
+    v[k] = cmadd_c<k, R, DIR>(e[k], o[k]);
   });
 }
 
