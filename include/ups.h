@@ -157,22 +157,27 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
 /* Schedule of the three column passes (y-forward, z-convolution,
  * y-inverse), which treat every x frequency kx independently.  With
  * `columns` = w > 0 they run slab by slab over kx in [0, w), [w, 2w), ...
- * (the last slab also takes the remainder), so that each slab's padded
- * spectrum is still in the device's last-level cache when the next pass
- * reads it; 0 runs each pass once over all columns.  The result does not
- * depend on the schedule (bitwise).  INVALID_ARG unless w is 0 or a positive
- * multiple of 16.  ups_plan_create picks a default from the problem size;
- * ups_plan_slab returns the current width (0 = one slab), or -1 for NULL. */
+ * (the last slab also takes the remainder); 0 runs each pass once over all
+ * columns.  With the side stream on (ups_plan_set_side_stream) and more than
+ * one slab, the z pass of each slab runs on a plan-owned stream beside the
+ * y passes of the other slabs on the caller's stream (forked and joined
+ * with events; everything is complete in the caller's stream order when the
+ * solve's last pass is).  The result does not depend on the schedule
+ * (bitwise).  INVALID_ARG unless w is 0 or a positive multiple of 16.
+ * ups_plan_create picks a default from the problem size (FP64 with at least
+ * 384 columns: 128-column slabs with the side stream on; otherwise one
+ * slab, side stream off); ups_plan_slab returns the current width (0 = one
+ * slab), or -1 for NULL. */
 ups_status ups_plan_set_slab(ups_plan_t plan, int columns);
 int ups_plan_slab(ups_plan_t plan);
 
 /* Each column pass runs over the largest multiple of 8 x (columns per
  * 128-byte line) x-frequencies in one launch and over the remaining columns
- * in a second, narrower launch.  With `enable` != 0 the second launch runs
- * on a plan-owned stream, forked from and joined back into the caller's
- * stream with events; 0 (the default: measured no faster at 512^3) puts it
- * on the caller's stream after the first.  Results are identical either
- * way. */
+ * in a second, narrower launch.  With one slab and `enable` != 0 the second
+ * launch runs on a plan-owned stream, forked from and joined back into the
+ * caller's stream with events; with several slabs `enable` != 0 pipelines
+ * them (see ups_plan_set_slab).  0 keeps every launch on the caller's
+ * stream.  Results are identical either way. */
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);
 
 /* Enqueue one pass of the solve on the bound work buffer W, for testing and

@@ -32,12 +32,17 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);
 ups_status set_error(ups_status s, const char* msg);
-// A second stream (default priority) and two events: the remainder launch of
-// a split column pass runs beside the main launch (fork on `fork`, join on
-// `join`).
+// A second stream (default priority) and its events.  With one column slab
+// the remainder launch of a split column pass runs beside the main launch
+// (fork on `fork`, join on `join`).  With several slabs the z pass runs on
+// the second stream, slab by slab, while the main stream runs the y passes
+// of the other slabs (ev[2 s]: y-forward of slab s done, ev[2 s + 1]: z of
+// slab s done).
 struct SideStream {
+  static constexpr int kMaxSlabs = 16;
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t ev[2 * kMaxSlabs] = {};
 };
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st, const SideStream* side);

@@ -214,3 +214,12 @@ def test_kernel_variant_listing():
     assert L.ups_plan_slab(h) == 16
     L.ups_plan_destroy(h)
     assert L.ups_plan_slab(None) == -1
+
+
+def test_default_schedule_pipelines_large_fp64_plans():
+    # an FP64 plan with >= 384 x-frequencies starts with 128-column slabs
+    # (pipelined over two streams); smaller or FP32 plans with one slab
+    from paper_2512_08555_amd.solver import Plan
+    assert Plan((8, 8, 300), 1.0 / 300, "f64", pad=(32, 32, 1024), setup=False).slab == 128
+    assert Plan((8, 8, 200), 1.0 / 200, "f64", pad=(32, 32, 512), setup=False).slab == 0
+    assert Plan((8, 8, 300), 1.0 / 300, "f32", pad=(32, 32, 1024), setup=False).slab == 0
