@@ -368,7 +368,8 @@ __global__ void k_twiddles(const double* __restrict__ src, int n, cx<T>* __restr
 // kTw2 x kTw2 block after them holds T[a][b] = exp(-2 pi i (a b mod M) / M),
 // so a thread's run of twiddles w^(q k), k = 0, 1, ..., is one row (one base
 // address plus constant offsets) and a wave's w^(k l) over lanes l is one
-// contiguous row as well.
+// contiguous row as well.  The later-stage tables of the wave-per-line
+// kernels (ztab.hpp) follow for M = 512 .. 4096.
 template <typename T>
 hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
   const size_t n = twiddle_entries(M);
@@ -385,6 +386,19 @@ hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
       tw[2 * i] = tw[2 * m];
       tw[2 * i + 1] = tw[2 * m + 1];
     }
+  const size_t z0 = (size_t)M + (size_t)kTw2 * kTw2;
+  const int nz = ztab_entries(M);
+  for (int i = 0; i < nz; ++i) {
+    long long m = 0;
+    switch (M) {
+      case 512: m = ztab_exponent<8>(i); break;
+      case 1024: m = ztab_exponent<16>(i); break;
+      case 2048: m = ztab_exponent<32>(i); break;
+      default: m = ztab_exponent<64>(i); break;
+    }
+    tw[2 * (z0 + i)] = tw[2 * m];
+    tw[2 * (z0 + i) + 1] = tw[2 * m + 1];
+  }
   GCHECK(hipMemcpyAsync(scratch, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL((k_twiddles<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
                      static_cast<const double*>(scratch), int(n), static_cast<cx<T>*>(dst));

@@ -4,6 +4,8 @@
 #include <cstddef>
 #include <vector>
 
+#include "ztab.hpp"
+
 namespace ups {
 
 // Byte offsets of the double-precision scratch arrays the builder uses
@@ -25,10 +27,11 @@ hipError_t build_green(bool f64, int kz, int ky, int kx, int gz, double h, int m
                        void* ghat, void* scratch, hipStream_t st);
 
 // dst[m] = exp(-2 pi i m / M), m < M, complex float or double; waits.
-// Complex entries of one axis's twiddle table: M (exp(-2 pi i m / M)) plus a
-// kTw2 x kTw2 block of products (see build_twiddles_t).
+// Complex entries of one axis's twiddle table: M (exp(-2 pi i m / M)), a
+// kTw2 x kTw2 block of products, then the later-stage tables of ztab.hpp
+// (see build_twiddles_t).
 constexpr int kTw2 = 64;
-inline size_t twiddle_entries(int M) { return (size_t)M + (size_t)kTw2 * kTw2; }
+inline size_t twiddle_entries(int M) { return (size_t)M + (size_t)kTw2 * kTw2 + (size_t)ztab_entries(M); }
 hipError_t build_twiddles(bool f64, int M, void* dst, void* scratch, hipStream_t st);
 
 }  // namespace ups

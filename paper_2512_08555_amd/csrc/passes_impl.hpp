@@ -98,14 +98,15 @@ __device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) 
 // mask marks the G_hat loads of the z pass, bit 6 the wave-per-line kernels
 // of pass 4 (bit 3 then covers its column kernels).  Measured on MI355X at
 // 512^3 (FP32 and FP64): nontemporal loads and stores in both forward passes
-// shorten them and the z pass after them, and nontemporal loads and stores
-// shorten the wave-per-line pass 4 and the x pass after it; every other
-// hint slows the pass it is in or the one after.
+// shorten them and the z pass after them, nontemporal loads and stores
+// shorten the wave-per-line pass 4 and the x pass after it, and nontemporal
+// stores shorten pass 5 a little; every other hint slows the pass it is in
+// or the one after.
 #ifndef UPS_NT_LOAD_MASK
 #define UPS_NT_LOAD_MASK 0x43
 #endif
 #ifndef UPS_NT_STORE_MASK
-#define UPS_NT_STORE_MASK 0x43
+#define UPS_NT_STORE_MASK 0x53
 #endif
 constexpr int kNtGhatBit = 5;
 constexpr int kNtYinvWaveBit = 6;

@@ -33,6 +33,7 @@
 // as products.
 #pragma once
 #include "passes_impl.hpp"
+#include "ztab.hpp"
 
 namespace ups {
 
@@ -57,23 +58,12 @@ struct ZWave {
   static constexpr int xfloats = cmax(cmax(E * S1, A * P2), (E - 1) * S4 + 64);
 };
 
-// Twiddles of the later stages from tables in LDS, built once per workgroup
-// from the length-M table (tw[m] = w_M^m):
-//   t2[l1 (E+1) + m1]       = w_M^(E l1 m1),  l1 < A, m1 < E   (stage 2)
-//   ta[(n0-1) (M/A) + a]    = w_M^(n0 a),     n0 < A, a < M/A  (inverse stage A)
-//   tb[b (E+1) + e]         = w_M^(A e b),    b, e < E         (inverse stage B)
-// Rows of E+1 entries put the lane groups that read different rows of t2
-// and tb in different banks.  One load per twiddle instead of products.
-// Table loads are issued in groups of kTabGroup between compiler fences, so
-// that the compiler does not hoist all of a stage's loads (and their
-// registers) ahead of the arithmetic.
+// Twiddles of the later stages from the tables of ztab.hpp, which the
+// workgroup copies into LDS from behind the axis's twiddle table: one load
+// per twiddle instead of products.  Table loads are issued in groups of
+// kTabGroup between compiler fences, so that the compiler does not hoist all
+// of a stage's loads (and their registers) ahead of the arithmetic.
 constexpr int kTabGroup = 2;
-template <int E>
-struct ZTab {
-  static constexpr int M = 64 * E, A = 64 / E;
-  static constexpr int n2 = A * (E + 1), na = (A - 1) * (M / A), nb = E * (E + 1);
-  static constexpr int o2 = 0, oa = n2, ob = n2 + na, total = n2 + na + nb;
-};
 // Complex elements per LDS column slot: room for the nz <= M/2 tile rows and
 // for one exchange (floats), with slot stride = 16 / CW (mod 16) so that the
 // 64-bit tile accesses of the CW columns fall in different banks.
@@ -122,24 +112,12 @@ __device__ __forceinline__ void wave_exchange(cx<T> (&v)[E], T* xf, WA waddr, RA
   wave_fence();
 }
 
+// Copy the ZTab tables of length M = 64 E into LDS: they follow the M
+// entries and the 64 x 64 product block of the axis table tw.
 template <typename T, int E>
 __device__ __forceinline__ void zw_fill_tables(cx<T>* tab, const cx<T>* tw, int t, int nthreads) {
-  using Z = ZTab<E>;
-  constexpr int M = Z::M, A = Z::A;
-  for (int i = t; i < Z::total; i += nthreads) {
-    int e;
-    if (i < Z::oa) {
-      const int l1 = i / (E + 1), m1 = i % (E + 1);
-      e = (E * l1 * m1) % M;
-    } else if (i < Z::ob) {
-      const int j = i - Z::oa;
-      e = (j / (M / A) + 1) * (j % (M / A));  // n0 a < M
-    } else {
-      const int j = i - Z::ob;
-      e = (A * (j / (E + 1)) * (j % (E + 1))) % M;
-    }
-    tab[i] = tw_at(tw, unsigned(e));
-  }
+  const cx<T>* src = tw + ZTab<E>::M + kTw2Row * kTw2Row;
+  for (int i = t; i < ZTab<E>::total; i += nthreads) tab[i] = src[i];
 }
 
 // Forward transform of one line held by a wave: on entry v[j] (j < E/2)
