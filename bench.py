@@ -29,7 +29,7 @@ PASS_NAMES = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
 KERNEL_SOURCES = ("paper_2512_08555_amd/csrc/passes_impl.hpp", "paper_2512_08555_amd/csrc/passes_f32.hip",
                   "paper_2512_08555_amd/csrc/passes_f32m.hip", "paper_2512_08555_amd/csrc/passes_f64.hip",
                   "paper_2512_08555_amd/csrc/zwave.hpp", "paper_2512_08555_amd/csrc/ywave.hpp",
-                  "paper_2512_08555_amd/csrc/xwave.hpp",
+                  "paper_2512_08555_amd/csrc/xwave.hpp", "paper_2512_08555_amd/csrc/ztab.hpp",
                   "paper_2512_08555_amd/csrc/dft.hpp",
                   "paper_2512_08555_amd/csrc/cplx.hpp")
 
