@@ -13,7 +13,7 @@ std::vector<PassVariant> variants_f32_pow2() {
       X_VARIANTS(float, 8, 8, 16, 2),       // mx = 128
       X_VARIANTS(float, 8, 16, 16, 2),      // mx = 256
       X_VARIANTS(float, 16, 16, 16, 2),     // mx = 512
-      XFW(float, 8, 4), XFW(float, 8, 8), XIW(float, 8, 8), XIW(float, 8, 4), XIW(float, 8, 16),   // mx = 1024
+      XFW(float, 8, 4), XFW(float, 8, 8), XIWM(float, 8, 8), XIWM(float, 8, 4), XIW(float, 8, 8), XIW(float, 8, 4),   // mx = 1024
       XF(float, 16, 32, 4, 1), XF(float, 16, 32, 8, 2), XF(float, 16, 32, 8, 1),
       XF(float, 32, 16, 8, 2), XF(float, 16, 32, 16, 2), XF(float, 16, 32, 16, 4),
       XI(float, 16, 32, 16, 4), XI(float, 16, 32, 4, 1), XI(float, 16, 32, 8, 1),

@@ -13,7 +13,7 @@ std::vector<PassVariant> variants_f64() {
       X_VARIANTS(double, 8, 8, 8, 2),
       X_VARIANTS(double, 8, 16, 8, 2),
       X_VARIANTS(double, 16, 16, 8, 2),
-      XFW(double, 8, 8), XFW(double, 8, 4), XIW(double, 8, 8), XIW(double, 8, 4),   // mx = 1024
+      XFW(double, 8, 8), XFW(double, 8, 4), XIWM(double, 8, 8), XIW(double, 8, 8),   // mx = 1024
       XF(double, 16, 32, 8, 2), XF(double, 16, 32, 8, 4),
       XI(double, 16, 32, 8, 2), XI(double, 16, 32, 8, 4),
       COL_VARIANTS(double, 4, 8, 8, 1),

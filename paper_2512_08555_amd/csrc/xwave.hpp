@@ -23,14 +23,24 @@
 
 namespace ups {
 
-template <typename T, int E, int RW>
+// LDS area of one wave in the inverse x pass: the exchanges, or (ML) the
+// whole half spectrum X[0..L].
+template <int E, bool ML>
+constexpr int xwinv_slot() {
+  constexpr int a = (ZWave<E>::xfloats + 1) / 2, b = 64 * E + 1;
+  return ML && b > a ? b : a;
+}
+
+// ML: load each X[k] once and take the mirrored X[L-k] from the wave's LDS
+// area, instead of loading it a second time from the row.
+template <typename T, int E, int RW, bool ML>
 __device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __restrict__ u, const PassArgs& a,
                                            unsigned bx, unsigned by) {
   using Z = ZWave<E>;
   constexpr int L = Z::M, A = Z::A, E2 = Z::E2;
   constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
   constexpr bool LT = zwave_lds_twiddles<E>();
-  constexpr int XS = (Z::xfloats + 1) / 2;  // complex elements of one wave's exchange area
+  constexpr int XS = xwinv_slot<E, ML>();  // complex elements of one wave's LDS area
   __shared__ cx<T> xs[RW * XS];
   __shared__ cx<T> twl[LT ? NR * 64 : 1];
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_x);  // table of length 2L
@@ -53,14 +63,39 @@ __device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __res
   // untangle; conj w_2L^k = conj w_2L^lane * conj w_2L^base
   const cx<T> wl = tw_at(tw, unsigned(lane));
   cx<T> v[E];
-  static_for<0, E>([&](auto ii) {
-    constexpr int i = decltype(ii)::value;
-    constexpr int base = 64 * (i / A) + E2 * (i % A);
-    const int k = lane + base;  // k < L, so L - k is in 1 .. L
-    const cx<T> xk = ld_cx<nt_load<4>()>(src + k);
-    const cx<T> xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
-    v[i] = (xk + xm) + mul_i<+1>(twiddle_c<base, 2 * L, +1>(cmulc(xk - xm, wl)));
-  });
+  if constexpr (ML) {
+    cx<T>* zs = reinterpret_cast<cx<T>*>(xf);
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      v[i] = ld_cx<nt_load<kNtXinvWaveBit>()>(src + (lane + 64 * (i / A) + E2 * (i % A)));
+    });
+    cx<T> xl = zero_c<T>();
+    if (lane == 0) xl = ld_cx<nt_load<kNtXinvWaveBit>()>(src + L);
+    wave_fence();
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      zs[lane + 64 * (i / A) + E2 * (i % A)] = v[i];
+    });
+    if (lane == 0) zs[L] = xl;
+    wave_fence();
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      constexpr int base = 64 * (i / A) + E2 * (i % A);
+      const cx<T> xk = v[i];
+      const cx<T> xm = conj(zs[L - (lane + base)]);
+      v[i] = (xk + xm) + mul_i<+1>(twiddle_c<base, 2 * L, +1>(cmulc(xk - xm, wl)));
+    });
+    wave_fence();
+  } else {
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      constexpr int base = 64 * (i / A) + E2 * (i % A);
+      const int k = lane + base;  // k < L, so L - k is in 1 .. L
+      const cx<T> xk = ld_cx<nt_load<4>()>(src + k);
+      const cx<T> xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
+      v[i] = (xk + xm) + mul_i<+1>(twiddle_c<base, 2 * L, +1>(cmulc(xk - xm, wl)));
+    });
+  }
   zw_inverse<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
 
   const int nx = a.nx;
@@ -187,29 +222,29 @@ void launchg_xwfwd(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
   hipLaunchKernelGGL((k_xwfwd_g<T, E, RW>), dim3(nblocks), dim3(64 * RW), 0, s, g);
 }
 
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool ML>
 __global__ void __launch_bounds__(64 * RW) k_xwinv(const cx<T>* __restrict__ W, T* __restrict__ u, PassArgs a) {
-  xwinv_body<T, E, RW>(W, u, a, blockIdx.x, blockIdx.y);
+  xwinv_body<T, E, RW, ML>(W, u, a, blockIdx.x, blockIdx.y);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool ML>
 __global__ void __launch_bounds__(64 * RW) k_xwinv_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
   const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
-  xwinv_body<T, E, RW>(static_cast<const cx<T>*>(group_in(g, e)), static_cast<T*>(group_out(g, e)), e.a,
-                       lin % gx, lin / gx);
+  xwinv_body<T, E, RW, ML>(static_cast<const cx<T>*>(group_in(g, e)), static_cast<T*>(group_out(g, e)), e.a,
+                           lin % gx, lin / gx);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool ML>
 void launch_xwinv(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
-  hipLaunchKernelGGL((k_xwinv<T, E, RW>), grid, dim3(64 * RW), 0, s, static_cast<const cx<T>*>(in),
+  hipLaunchKernelGGL((k_xwinv<T, E, RW, ML>), grid, dim3(64 * RW), 0, s, static_cast<const cx<T>*>(in),
                      static_cast<T*>(out), a);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool ML>
 void launchg_xwinv(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_xwinv_g<T, E, RW>), dim3(nblocks), dim3(64 * RW), 0, s, g);
+  hipLaunchKernelGGL((k_xwinv_g<T, E, RW, ML>), dim3(nblocks), dim3(64 * RW), 0, s, g);
 }
 template <typename T, int E, int RW>
 constexpr int xwfwd_lds_bytes() {
@@ -217,11 +252,11 @@ constexpr int xwfwd_lds_bytes() {
   constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
   return int(sizeof(cx<T>)) * (RW * xwfwd_slot<E>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool ML>
 constexpr int xwave_lds_bytes() {
   constexpr int A = 64 / E;
   constexpr int NR = 31 - __builtin_clz(E > A ? E : A);
-  return int(sizeof(cx<T>)) * (RW * ((ZWave<E>::xfloats + 1) / 2) + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
+  return int(sizeof(cx<T>)) * (RW * xwinv_slot<E, ML>() + (zwave_lds_twiddles<E>() ? NR * 64 : 1));
 }
 
 // mx = 128 E; P = E, Q = 64 (half length 64 E), tile = RW rows (one wave
@@ -230,8 +265,10 @@ constexpr int xwave_lds_bytes() {
   PassVariant{PASS_XFWD, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW,                               \
               xwfwd_lds_bytes<T, E, RW>(),                                                        \
               "xfwd_" #T "_w" #E "_r" #RW, &launch_xwfwd<T, E, RW>, &launchg_xwfwd<T, E, RW>}
-#define XIW(T, E, RW)                                                                             \
-  PassVariant{PASS_XINV, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW, xwave_lds_bytes<T, E, RW>(),   \
-              "xinv_" #T "_w" #E "_r" #RW, &launch_xwinv<T, E, RW>, &launchg_xwinv<T, E, RW>}
+#define XIWV(T, E, RW, SUF, ML)                                                                   \
+  PassVariant{PASS_XINV, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW, xwave_lds_bytes<T, E, RW, ML>(), \
+              "xinv_" #T "_w" #E "_r" #RW SUF, &launch_xwinv<T, E, RW, ML>, &launchg_xwinv<T, E, RW, ML>}
+#define XIW(T, E, RW) XIWV(T, E, RW, "", false)
+#define XIWM(T, E, RW) XIWV(T, E, RW, "_m", true)
 
 }  // namespace ups
