@@ -167,6 +167,20 @@ def batch_leg(reps=10):
             "launches_per_pass": b.launches(), "setup_ms": setup_ms}
 
 
+def c2_leg(n=256, reps=10):
+    """The plain FP64 GPU path on the 256^3 blob-plus-noise source (padded
+    512^3): ms per whole solve, and its grid points per second."""
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.solver import Plan
+    f = torch.from_numpy(workloads.config_blobs_noise(n, 2)).cuda()
+    plan = Plan((n, n, n), 1.0 / n, "f64")
+    u = torch.empty_like(f)
+    ms = time_solve(plan, f, u, reps, 3)
+    return {"n": n, "precision": "f64", "ms_per_solve": ms, "pts_per_s": n ** 3 / (ms * 1e-3),
+            "hbm_gbs_model": plan.model_bytes(-1) / (ms * 1e-3) / 1e9}
+
+
 def grad_leg(n=256, reps=5):
     """Differentiable workload: 256^3 FP32 forward solve + loss + backward
     through the hand-written adjoint (torch.autograd)."""
@@ -285,6 +299,9 @@ def main():
         }
         del p64
 
+    if not args.no_f64:
+        extra["c2_f64_256"] = c2_leg()
+        torch.cuda.empty_cache()
     if not args.no_batch:
         extra["batch"] = batch_leg()
         torch.cuda.empty_cache()
