@@ -109,8 +109,9 @@ def time_solve(plan, f, u, steps, warmup):
 
 
 def cpu_baseline(n_sample=256):
-    """The CPU oracle (scipy.fft, FP64, all host threads) on a bounded sample:
-    one n_sample^3 solve of the same source recipe; G_hat precomputed."""
+    """The CPU oracle (scipy.fft, FP64, up to 16 host threads) on a bounded
+    sample: repeated n_sample^3 solves of the same source recipe (about 10 s
+    of CPU work); G_hat precomputed."""
     import oracle
     from paper_2512_08555_amd import workloads
     workers = len(os.sched_getaffinity(0))
@@ -119,12 +120,16 @@ def cpu_baseline(n_sample=256):
     f = workloads.config_blobs_noise(n_sample, 2)
     M = (2 * n_sample,) * 3
     G = oracle.green_spectrum_raw(M)
-    t0 = time.perf_counter()
-    oracle.solve(f, h, G_hat_raw=G, workers=workers)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample ** 3 / dt, "unit": "grid points/s", "cores": workers, "kind": "oracle",
-            "sample": "one %d^3 FP64 solve by oracle.solve (pruned scipy.fft, %d workers), "
-                      "G_hat precomputed; %.2f s" % (n_sample, workers, dt)}
+    # repeat the solve until about 10 s of CPU work (at most 40 solves)
+    reps, dt = 0, 0.0
+    while reps < 40 and (dt < 10.0 or reps < 1):
+        t0 = time.perf_counter()
+        oracle.solve(f, h, G_hat_raw=G, workers=workers)
+        dt += time.perf_counter() - t0
+        reps += 1
+    return {"value": reps * n_sample ** 3 / dt, "unit": "grid points/s", "cores": workers, "kind": "oracle",
+            "sample": "%d solves of the %d^3 FP64 source by oracle.solve (pruned scipy.fft, %d workers), "
+                      "G_hat precomputed; %.1f s" % (reps, n_sample, workers, dt)}
 
 
 def batch_leg(reps=10):
