@@ -9,7 +9,8 @@
 // X[k] and X[L-k] are contiguous across the wave), which is the layout the
 // inverse stages of the z pass take; those stages leave output pair
 // m = l + 64 f (f < E/2) in register f, and only m < L/2 is kept (nx <= L).
-// No staging and no barrier: the row is contiguous in W.
+// No tile staging and no barrier: the row is contiguous in W.  The "_m"
+// variants load each X[k] once and take X[L-k] from the wave's LDS area.
 //
 // Pass 1 the same way: the real row packed as z[m] = f[2m] + i f[2m+1]
 // (m < nx/2 <= L/2, the zero padding is the upper half), the forward stages
