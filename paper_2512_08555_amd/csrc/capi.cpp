@@ -278,21 +278,26 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
     // (bound by memory)
     void* ws[SideStream::kMaxSlabs];
     PassArgs b[SideStream::kMaxSlabs];
+    hipError_t ee = hipSuccess;  // first failing event call
+    auto chk = [&](hipError_t r) {
+      if (ee == hipSuccess) ee = r;
+    };
     for (int s = 0; s < ns; ++s) b[s] = slab_args(g, a, slab, s, work, &ws[s]);
     for (int s = 0; s < ns; ++s) {
       enqueue_colpass(g, var[1], b[s], ws[s], st);
-      hipEventRecord(side->ev[2 * s], st);
-      hipStreamWaitEvent(side->s, side->ev[2 * s], 0);
+      chk(hipEventRecord(side->ev[2 * s], st));
+      chk(hipStreamWaitEvent(side->s, side->ev[2 * s], 0));
       enqueue_colpass(g, var[2], b[s], ws[s], side->s);
-      hipEventRecord(side->ev[2 * s + 1], side->s);
+      chk(hipEventRecord(side->ev[2 * s + 1], side->s));
     }
     for (int s = 0; s < ns; ++s) {
-      hipStreamWaitEvent(st, side->ev[2 * s + 1], 0);
+      chk(hipStreamWaitEvent(st, side->ev[2 * s + 1], 0));
       enqueue_colpass(g, var[3], b[s], ws[s], st);
     }
     var[4]->launch(a, work, u, st);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    if (e == hipSuccess) e = ee;
+    if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "solve enqueue failed: %s", hipGetErrorString(e));
     return UPS_OK;
   }
   for (int s = 0; s < ns; ++s) {

@@ -102,3 +102,38 @@ def test_wave_pass_aligned_columns_plus_remainder(k, prec, M, name):
     ref = oracle.solve(f, h, M=pad)
     err = float(np.abs(u - ref).max() / np.abs(ref).max())
     assert err < (1e-12 if prec == "f64" else 3e-6), (name, err)
+
+
+def _x_cases():
+    out = []
+    for prec in ("f32", "f64"):
+        for k in (0, 4):
+            for nm in kernel_variants(k, prec, 1024):
+                out.append((k, prec, nm))
+    return out
+
+
+try:
+    X_CASES = _x_cases()
+except Exception:  # library not built: collection must still work
+    X_CASES = []
+
+
+@pytest.mark.parametrize("k,prec,name", X_CASES)
+@pytest.mark.parametrize("nx", [511, 301])
+def test_x_pass_odd_row_length(k, prec, name, nx):
+    """Odd nx: the packed row ends in a lone real value (scalar loads and stores)."""
+    shape, pad = (6, 10, nx), (32, 32, 1024)
+    print("[case] odd nx %d %s pass %d %s" % (nx, name, k, prec), flush=True)
+    rng = np.random.default_rng(nx + k)
+    f = rng.standard_normal(shape)
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    h = 1.0 / nx
+    plan = Plan(shape, h, prec, pad=pad)
+    plan.set_kernel(k, name)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    ref = oracle.solve(f, h, M=pad)
+    err = float(np.abs(u - ref).max() / np.abs(ref).max())
+    assert err < (1e-12 if prec == "f64" else 3e-6), (name, err)
