@@ -163,7 +163,9 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
  * y passes of the other slabs on the caller's stream (forked and joined
  * with events; everything is complete in the caller's stream order when the
  * solve's last pass is).  The result does not depend on the schedule
- * (bitwise).  INVALID_ARG unless w is 0 or a positive multiple of 16.
+ * beyond rounding: a slab's last columns may run through another compiled
+ * variant of the same pass than with one slab, which can differ in the
+ * last bit.  INVALID_ARG unless w is 0 or a positive multiple of 16.
  * ups_plan_create picks a default from the problem size (FP64 with at least
  * 384 columns: 128-column slabs with the side stream on; otherwise one
  * slab, side stream off); ups_plan_slab returns the current width (0 = one
@@ -177,7 +179,7 @@ int ups_plan_slab(ups_plan_t plan);
  * launch runs on a plan-owned stream, forked from and joined back into the
  * caller's stream with events; with several slabs `enable` != 0 pipelines
  * them (see ups_plan_set_slab).  0 keeps every launch on the caller's
- * stream.  Results are identical either way. */
+ * stream.  Results are identical either way (the same kernels run). */
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);
 
 /* Enqueue one pass of the solve on the bound work buffer W, for testing and
