@@ -246,7 +246,7 @@ def main():
                     help="also run a 2 GiB copy kernel (for counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
 

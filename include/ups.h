@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   UPS_OK = 0,
   UPS_ERR_INVALID_ARG = 1, /* null pointer, bad size, misaligned pointer */
-  UPS_ERR_UNSUPPORTED = 2, /* valid problem this build does not handle */
+  UPS_ERR_UNSUPPORTED = 2, /* valid problem the library does not handle */
   UPS_ERR_WORKSPACE = 3,   /* caller buffer smaller than ups_*_sizes asked */
   UPS_ERR_DEVICE = 4,      /* no usable gfx950 device, or a HIP call failed */
   UPS_ERR_NONFINITE = 5,   /* reserved: non-finite input detected */
@@ -56,7 +56,7 @@ typedef enum {
 } ups_status;
 
 /* Boundary condition per axis side (Sec. 2.2: unbounded, periodic, even =
- * homogeneous Neumann, odd = homogeneous Dirichlet).  This build solves
+ * homogeneous Neumann, odd = homogeneous Dirichlet).  The library solves
  * UPS_BC_UNB on all six sides; anything else is UPS_ERR_UNSUPPORTED. */
 typedef enum { UPS_BC_UNB = 0, UPS_BC_PER = 1, UPS_BC_EVEN = 2, UPS_BC_ODD = 3 } ups_bc;
 
