@@ -198,10 +198,13 @@ ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long l
  * and of the whole solve for pass = -1.  Returns 0 on a bad argument. */
 double ups_plan_model_bytes(ups_plan_t plan, int pass);
 
-/* Time every compiled kernel variant of each pass on this plan's bound
- * buffers (HIP events on `stream`; the work buffer's contents are
- * overwritten) and keep the fastest.  Variants beyond the first are skipped
- * once `budget_ms` of kernel time is spent.  The choices go to a process-wide
+/* Time every compiled kernel variant of each pass, pass by pass, inside
+ * whole solves on this plan's bound buffers with the current choices for
+ * the other passes and the plan's schedule (HIP events on `stream`; the
+ * work buffer's contents are overwritten; best of two runs of 5 solves).
+ * A variant replaces the current choice only if it is faster by more than
+ * 1%.  Variants other than the current choice are skipped once `budget_ms`
+ * of GPU time is spent.  The choices go to a process-wide
  * cache used by later plans and batches of the same (pass, precision,
  * padded length); with the environment variable UPS_TUNE_CACHE set to a
  * file path the cache is loaded from and saved to that JSON file.  Waits for

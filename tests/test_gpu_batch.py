@@ -124,3 +124,19 @@ def test_autotune_keeps_results_correct(tmp_path, monkeypatch):
     assert all(isinstance(n, str) for n in names)
     u = plan.solve(_dev(f, "f32")).cpu().numpy().astype(np.float64)
     assert _rel_inf(u, oracle.solve(f, 1 / 64)) < 3e-6
+
+
+def test_autotune_pipelined_fp64_plan():
+    # an FP64 plan with 513 x-frequencies runs the two-stream slab schedule;
+    # tuning times whole solves in that schedule and keeps results correct
+    from paper_2512_08555_amd.solver import Plan
+    _announce("autotune 24x24x300 f64 pipelined")
+    rng = np.random.default_rng(3)
+    shape, pad = (24, 24, 300), (64, 64, 1024)
+    f = rng.standard_normal(shape)
+    plan = Plan(shape, 1 / 300, "f64", pad=pad)
+    assert plan.slab == 128
+    names = plan.autotune(budget_ms=200.0)
+    assert len(names) == 5 and all(isinstance(n, str) for n in names)
+    u = plan.solve(_dev(f, "f64")).cpu().numpy()
+    assert _rel_inf(u, oracle.solve(f, 1 / 300, M=pad)) < 1e-12
