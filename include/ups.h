@@ -203,8 +203,11 @@ double ups_plan_model_bytes(ups_plan_t plan, int pass);
  * the other passes and the plan's schedule (HIP events on `stream`; the
  * work buffer's contents are overwritten; best of two runs of 5 solves).
  * A variant replaces the current choice only if it is faster by more than
- * 1%.  Variants other than the current choice are skipped once `budget_ms`
- * of GPU time is spent.  The choices go to a process-wide
+ * 1%.  Plans with at least 256 x-frequencies then also try one slab and
+ * 128- or 256-column slabs pipelined over two streams (ups_plan_set_slab)
+ * and keep the fastest schedule, by the same rule (the schedule is kept in
+ * the plan only).  Candidates other than the current choice are skipped
+ * once `budget_ms` of GPU time is spent.  The choices go to a process-wide
  * cache used by later plans and batches of the same (pass, precision,
  * padded length); with the environment variable UPS_TUNE_CACHE set to a
  * file path the cache is loaded from and saved to that JSON file.  Waits for

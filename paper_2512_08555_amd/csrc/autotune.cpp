@@ -166,6 +166,34 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
     load_locked();
     g_cache[key_of(kKinds[k], g.f64, len[k])] = best->name;
   }
+  // then the column schedule: one slab, or 128- or 256-column slabs
+  // pipelined over two streams (plans with at least 256 columns)
+  if (err == hipSuccess && g.kx >= 256) {
+    const int cur_slab = plan->slab;
+    const bool cur_side = plan->use_side;
+    float best_ms = 0.f;
+    err = time_solves(&best_ms);
+    int best_slab = cur_slab;
+    bool best_side = cur_side;
+    const int slabs[3] = {0, 128, 256};
+    for (int i = 0; i < 3 && err == hipSuccess; ++i) {
+      const int sl = slabs[i];
+      const bool sd = sl > 0;
+      if ((sl == cur_slab && sd == cur_side) || spent > budget_ms || (sl > 0 && sl >= g.kx)) continue;
+      plan->slab = sl;
+      plan->use_side = sd;
+      side = plan->use_side ? &plan->side : nullptr;
+      float ms = 0.f;
+      err = time_solves(&ms);
+      if (err == hipSuccess && ms < 0.99f * best_ms) {
+        best_ms = ms;
+        best_slab = sl;
+        best_side = sd;
+      }
+    }
+    plan->slab = best_slab;
+    plan->use_side = best_side;
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (err != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(err));
