@@ -96,23 +96,25 @@ __device__ __forceinline__ void st_at(cx<T>* ubase, unsigned byte_off, cx<T> v) 
 // measurement: bit k of the load (store) mask marks pass k's data loads
 // (stores), k = 0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv; bit 5 of the load
 // mask marks the G_hat loads of the z pass, bit 6 the wave-per-line kernels
-// of pass 4 (bit 3 then covers its column kernels), bit 7 the loads of the
-// pass-5 kernel that takes mirrored values from LDS.  Measured on MI355X at
+// of pass 4 and bit 7 those of pass 5 (bits 3 and 4 then cover the column
+// and four-step kernels; for pass 5 the loads of bit 7 are those of the
+// variant that takes mirrored values from LDS).  Measured on MI355X at
 // 512^3 (FP32 and FP64): nontemporal loads and stores in both forward passes
 // shorten them and the z pass after them, nontemporal loads and stores
 // shorten the wave-per-line pass 4 and the x pass after it, and nontemporal
-// stores shorten pass 5 a little, as do nontemporal loads in the pass-5
-// kernel that reads each value once; every other hint slows the pass it is
-// in or the one after.
+// stores shorten the wave-per-row pass 5 a little, as do nontemporal loads
+// in its variant that reads each value once; every other hint slows the
+// pass it is in or the one after (nontemporal stores in the four-step
+// pass 5 slow the small solves of a batch by about 6%).
 #ifndef UPS_NT_LOAD_MASK
 #define UPS_NT_LOAD_MASK 0xC3
 #endif
 #ifndef UPS_NT_STORE_MASK
-#define UPS_NT_STORE_MASK 0x53
+#define UPS_NT_STORE_MASK 0xC3
 #endif
 constexpr int kNtGhatBit = 5;
 constexpr int kNtYinvWaveBit = 6;
-constexpr int kNtXinvWaveBit = 7;  // loads of the inverse x kernel that reads each value once
+constexpr int kNtXinvWaveBit = 7;  // wave-per-row pass 5: stores, and loads of the variant reading each value once
 template <int K>
 constexpr bool nt_load() { return ((UPS_NT_LOAD_MASK) >> K) & 1; }
 template <int K>

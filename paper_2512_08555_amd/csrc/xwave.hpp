@@ -103,14 +103,14 @@ __device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __res
   if (nx == L) {  // every pair m < L/2 is inside the row
     static_for<0, E / 2>([&](auto ff) {
       constexpr int f = decltype(ff)::value;
-      st_cx<nt_store<4>()>(reinterpret_cast<cx<T>*>(dst + 2 * (lane + 64 * f)), v[f]);
+      st_cx<nt_store<kNtXinvWaveBit>()>(reinterpret_cast<cx<T>*>(dst + 2 * (lane + 64 * f)), v[f]);
     });
   } else {
     static_for<0, E / 2>([&](auto ff) {
       constexpr int f = decltype(ff)::value;
       const int m = lane + 64 * f;
-      if (2 * m < nx) st_r<nt_store<4>()>(dst + 2 * m, v[f].re);
-      if (2 * m + 1 < nx) st_r<nt_store<4>()>(dst + 2 * m + 1, v[f].im);
+      if (2 * m < nx) st_r<nt_store<kNtXinvWaveBit>()>(dst + 2 * m, v[f].re);
+      if (2 * m + 1 < nx) st_r<nt_store<kNtXinvWaveBit>()>(dst + 2 * m + 1, v[f].im);
     });
   }
 }
