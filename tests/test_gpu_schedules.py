@@ -42,3 +42,33 @@ def test_schedules_match_oracle_and_each_other(prec):
                 rel = float(np.abs(un - base).max() / np.abs(base).max())
                 assert rel <= (4e-16 if prec == "f64" else 2e-7), (slab, side, rel)
 
+
+
+@pytest.mark.parametrize("prec,slab,side", [("f64", 128, True), ("f32", 0, False), ("f32", 128, True)])
+def test_solve_captured_in_a_graph(prec, slab, side):
+    """A solve captured in a HIP graph (two-stream pipelined schedule included)
+    gives the eager result on every replay, with eager work between replays."""
+    shape, pad = (16, 20, 300), (32, 64, 1024)
+    rng = np.random.default_rng(31)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    f = torch.from_numpy(rng.standard_normal(shape)).to("cuda", dt)
+    plan = Plan(shape, 1.0 / 300, prec, pad=pad)
+    plan.slab = slab
+    plan.set_side_stream(side)
+    print("[case] graph %s slab %d side %s" % (prec, slab, side), flush=True)
+    ref = plan.solve(f)
+    torch.cuda.synchronize()
+    u = torch.empty_like(f)
+    cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        plan.solve(f, out=u, stream=cap)
+    for rep in range(3):
+        u.zero_()
+        tmp = plan.solve(f * 2.0)            # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        tol = 1e-15 if prec == "f64" else 1e-7
+        assert float((u - ref).abs().max() / ref.abs().max()) <= tol, rep
+        assert float((tmp - 2.0 * ref).abs().max() / ref.abs().max()) < (1e-14 if prec == "f64" else 1e-6)
