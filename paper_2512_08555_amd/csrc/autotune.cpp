@@ -166,8 +166,9 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
     load_locked();
     g_cache[key_of(kKinds[k], g.f64, len[k])] = best->name;
   }
-  // then the column schedule: one slab, or 128- or 256-column slabs
-  // pipelined over two streams (plans with at least 256 columns)
+  // then the column schedule: one slab on one or two streams, or 128- or
+  // 256-column slabs pipelined over two streams (plans with at least 256
+  // columns)
   if (err == hipSuccess && g.kx >= 256) {
     const int cur_slab = plan->slab;
     const bool cur_side = plan->use_side;
@@ -175,10 +176,11 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
     err = time_solves(&best_ms);
     int best_slab = cur_slab;
     bool best_side = cur_side;
-    const int slabs[3] = {0, 128, 256};
-    for (int i = 0; i < 3 && err == hipSuccess; ++i) {
+    const int slabs[4] = {0, 0, 128, 256};
+    const bool sides[4] = {false, true, true, true};
+    for (int i = 0; i < 4 && err == hipSuccess; ++i) {
       const int sl = slabs[i];
-      const bool sd = sl > 0;
+      const bool sd = sides[i];
       if ((sl == cur_slab && sd == cur_side) || spent > budget_ms || (sl > 0 && sl >= g.kx)) continue;
       plan->slab = sl;
       plan->use_side = sd;

@@ -206,7 +206,12 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
 // of the others; measured at 512^3 that takes FP64 from 6.29 to 6.12 ms
 // with 128-column slabs and slows FP32 (3.09 -> 3.13 ms), so FP64 plans with
 // at least 384 columns start with 128-column slabs on two streams.
+// With one slab, running the narrow remainder launches of the three column
+// passes on the second stream (enqueue_solve) takes FP64 at 256^3 from 0.739
+// to 0.729 ms and leaves FP32 unchanged (2.995 ms at 512^3), so FP64 plans
+// turn the second stream on by default.
 int default_slab(const PlanGeom& g) { return g.f64 && g.kx >= 384 ? 128 : 0; }
+bool default_side(const PlanGeom& g) { return g.f64 || default_slab(g) > 0; }
 
 int slab_count(const PlanGeom& g, int slab) {
   if (slab <= 0 || slab >= g.kx) return 1;
@@ -300,6 +305,32 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
     if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "solve enqueue failed: %s", hipGetErrorString(e));
     return UPS_OK;
   }
+  if (side && side->s && ns == 1) {
+    // one slab with a second stream: the few columns past the aligned launch
+    // width go through all three column passes on the side stream, beside the
+    // main launches, with one fork after the x pass and one join before the
+    // last one
+    const int align = 8 * (128 / int(2 * g.elem));
+    const int kmain = a.kx / align * align;
+    const PassVariant* nv[3] = {narrow_variant(*var[1]), narrow_variant(*var[2]), narrow_variant(*var[3])};
+    if (kmain > 0 && kmain < a.kx && nv[0] && nv[1] && nv[2]) {
+      void* wm = nullptr;
+      void* wr = nullptr;
+      const PassArgs am = column_range(g, a, 0, kmain, work, &wm);
+      const PassArgs ar = column_range(g, a, kmain, a.kx - kmain, work, &wr);
+      hipError_t ee = hipEventRecord(side->fork, st);
+      if (ee == hipSuccess) ee = hipStreamWaitEvent(side->s, side->fork, 0);
+      for (int p = 0; p < 3 && ee == hipSuccess; ++p) nv[p]->launch(ar, wr, wr, side->s);
+      if (ee == hipSuccess) ee = hipEventRecord(side->join, side->s);
+      for (int p = 1; p <= 3 && ee == hipSuccess; ++p) var[p]->launch(am, wm, wm, st);
+      if (ee == hipSuccess) ee = hipStreamWaitEvent(st, side->join, 0);
+      if (ee == hipSuccess) var[4]->launch(a, work, u, st);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = ee;
+      if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "solve enqueue failed: %s", hipGetErrorString(e));
+      return UPS_OK;
+    }
+  }
   for (int s = 0; s < ns; ++s) {
     void* ws = nullptr;
     const PassArgs b = slab_args(g, a, slab, s, work, &ws);
@@ -362,7 +393,7 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   p->prob = *prob;
   p->g = g;
   p->slab = default_slab(g);
-  p->use_side = p->slab > 0;
+  p->use_side = default_side(g);
   for (int i = 0; i < 5; ++i) {
     p->var[i] = tuned_variant(kinds[i], g.f64, len[i], g);
     if (!p->var[i]) {

@@ -47,6 +47,7 @@ struct SideStream {
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st, const SideStream* side);
 int default_slab(const PlanGeom& g);
+bool default_side(const PlanGeom& g);
 void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
                      const SideStream* side = nullptr);
 int slab_count(const PlanGeom& g, int slab);
