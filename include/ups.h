@@ -183,6 +183,8 @@ int ups_plan_slab(ups_plan_t plan);
  * ups_plan_set_slab).  0 keeps every launch on the caller's stream.
  * Results are identical either way (the same kernels run). */
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);
+/* 1 if the side stream is on for this plan, 0 if off, -1 for NULL. */
+int ups_plan_side_stream(ups_plan_t plan);
 
 /* Enqueue one pass of the solve on the bound work buffer W, for testing and
  * per-kernel timing: pass 0 reads the real array `in` and writes W; passes

@@ -61,6 +61,7 @@ SIGNATURES = {
     "ups_plan_set_slab": (C.c_int, [C.c_void_p, C.c_int]),
     "ups_plan_slab": (C.c_int, [C.c_void_p]),
     "ups_plan_set_side_stream": (C.c_int, [C.c_void_p, C.c_int]),
+    "ups_plan_side_stream": (C.c_int, [C.c_void_p]),
     "ups_plan_model_bytes": (C.c_double, [C.c_void_p, C.c_int]),
     "ups_plan_destroy": (C.c_int, [C.c_void_p]),
     "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),

@@ -543,6 +543,8 @@ ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable) {
   return ok();
 }
 
+int ups_plan_side_stream(ups_plan_t plan) { return plan ? (plan->use_side ? 1 : 0) : -1; }
+
 double ups_plan_model_bytes(ups_plan_t plan, int pass) {
   if (!plan || pass < -1 || pass > 4) return 0.0;
   return model_bytes(plan->g, pass);

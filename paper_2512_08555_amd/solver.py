@@ -145,8 +145,15 @@ class Plan:
         capi.check(capi.lib().ups_plan_set_slab(self._h, int(columns)))
 
     def set_side_stream(self, enable):
-        """Run the narrow remainder launches on a second stream (default) or not."""
+        """Run the narrow remainder launches (one slab) or the z passes of the
+        slabs (several) on a second stream, or keep every launch on the
+        caller's stream."""
         capi.check(capi.lib().ups_plan_set_side_stream(self._h, int(bool(enable))))
+
+    @property
+    def side_stream(self):
+        """Whether the plan uses its second stream."""
+        return capi.lib().ups_plan_side_stream(self._h) == 1
 
     def model_bytes(self, k=-1):
         return capi.lib().ups_plan_model_bytes(self._h, int(k))
