@@ -167,8 +167,8 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
  * variant of the same pass than with one slab, which can differ in the
  * last bit.  INVALID_ARG unless w is 0 or a positive multiple of 16.
  * ups_plan_create picks a default from the problem size (FP64 with at least
- * 384 columns: 128-column slabs with the side stream on; other FP64 plans:
- * one slab, side stream on; FP32: one slab, side stream off);
+ * 384 columns: 128-column slabs with the side stream on; other plans: one
+ * slab, side stream on);
  * ups_plan_slab returns the current width (0 = one slab), or -1 for NULL. */
 ups_status ups_plan_set_slab(ups_plan_t plan, int columns);
 int ups_plan_slab(ups_plan_t plan);
@@ -177,9 +177,9 @@ int ups_plan_slab(ups_plan_t plan);
  * 128-byte line) x-frequencies in one launch and over the remaining columns
  * in a second, narrower launch.  With one slab and `enable` != 0 the
  * narrow launches of all three column passes run on a plan-owned stream,
- * forked from the caller's stream after the x pass and joined back before
- * the inverse x pass with events (ups_run_pass forks and joins around the
- * one pass); with several slabs `enable` != 0 pipelines them (see
+ * forked from the caller's stream after the x pass (FP64) or after the main
+ * y-forward launch (FP32) and joined back before the inverse x pass with
+ * events (ups_run_pass forks and joins around the one pass); with several slabs `enable` != 0 pipelines them (see
  * ups_plan_set_slab).  0 keeps every launch on the caller's stream.
  * Results are identical either way (the same kernels run). */
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);

@@ -207,11 +207,12 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
 // with 128-column slabs and slows FP32 (3.09 -> 3.13 ms), so FP64 plans with
 // at least 384 columns start with 128-column slabs on two streams.
 // With one slab, running the narrow remainder launches of the three column
-// passes on the second stream (enqueue_solve) takes FP64 at 256^3 from 0.739
-// to 0.729 ms and leaves FP32 unchanged (2.995 ms at 512^3), so FP64 plans
-// turn the second stream on by default.
+// passes on the second stream (enqueue_solve) takes FP64 at 256^3 from 0.741
+// to 0.733 ms (forked after the x pass) and FP32 at 512^3 from 3.000 to
+// 2.984 ms (forked after the main y-forward launch), so every plan starts
+// with the second stream on.
 int default_slab(const PlanGeom& g) { return g.f64 && g.kx >= 384 ? 128 : 0; }
-bool default_side(const PlanGeom& g) { return g.f64 || default_slab(g) > 0; }
+bool default_side(const PlanGeom&) { return true; }
 
 int slab_count(const PlanGeom& g, int slab) {
   if (slab <= 0 || slab >= g.kx) return 1;
@@ -318,11 +319,16 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
       void* wr = nullptr;
       const PassArgs am = column_range(g, a, 0, kmain, work, &wm);
       const PassArgs ar = column_range(g, a, kmain, a.kx - kmain, work, &wr);
+      // FP32 forks after the main y-forward launch, so that the narrow
+      // launches run beside the z pass (bound by arithmetic) rather than the
+      // y pass (bound by memory); FP64 forks after the x pass
+      const int late = g.f64 ? 0 : 1;
+      if (late) var[1]->launch(am, wm, wm, st);
       hipError_t ee = hipEventRecord(side->fork, st);
       if (ee == hipSuccess) ee = hipStreamWaitEvent(side->s, side->fork, 0);
       for (int p = 0; p < 3 && ee == hipSuccess; ++p) nv[p]->launch(ar, wr, wr, side->s);
       if (ee == hipSuccess) ee = hipEventRecord(side->join, side->s);
-      for (int p = 1; p <= 3 && ee == hipSuccess; ++p) var[p]->launch(am, wm, wm, st);
+      for (int p = 1 + late; p <= 3 && ee == hipSuccess; ++p) var[p]->launch(am, wm, wm, st);
       if (ee == hipSuccess) ee = hipStreamWaitEvent(st, side->join, 0);
       if (ee == hipSuccess) var[4]->launch(a, work, u, st);
       hipError_t e = hipGetLastError();

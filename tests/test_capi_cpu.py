@@ -218,16 +218,15 @@ def test_kernel_variant_listing():
 
 def test_default_schedule_pipelines_large_fp64_plans():
     # an FP64 plan with >= 384 x-frequencies starts with 128-column slabs
-    # pipelined over two streams; smaller FP64 plans with one slab and the
-    # remainder launches on the second stream; FP32 plans with one slab on
-    # one stream
+    # pipelined over two streams; other plans with one slab and the
+    # remainder launches on the second stream
     from paper_2512_08555_amd.solver import Plan
     big64 = Plan((8, 8, 300), 1.0 / 300, "f64", pad=(32, 32, 1024), setup=False)
     small64 = Plan((8, 8, 200), 1.0 / 200, "f64", pad=(32, 32, 512), setup=False)
     big32 = Plan((8, 8, 300), 1.0 / 300, "f32", pad=(32, 32, 1024), setup=False)
     assert (big64.slab, big64.side_stream) == (128, True)
     assert (small64.slab, small64.side_stream) == (0, True)
-    assert (big32.slab, big32.side_stream) == (0, False)
-    big32.set_side_stream(True)
-    assert big32.side_stream
+    assert (big32.slab, big32.side_stream) == (0, True)
+    big32.set_side_stream(False)
+    assert not big32.side_stream
     assert capi.lib().ups_plan_side_stream(None) == -1

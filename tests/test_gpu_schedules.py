@@ -44,7 +44,8 @@ def test_schedules_match_oracle_and_each_other(prec):
 
 
 
-@pytest.mark.parametrize("prec,slab,side", [("f64", 128, True), ("f32", 0, False), ("f32", 128, True)])
+@pytest.mark.parametrize("prec,slab,side", [("f64", 128, True), ("f64", 0, True), ("f32", 0, False),
+                                            ("f32", 0, True), ("f32", 128, True)])
 def test_solve_captured_in_a_graph(prec, slab, side):
     """A solve captured in a HIP graph (two-stream pipelined schedule included)
     gives the eager result on every replay, with eager work between replays."""
