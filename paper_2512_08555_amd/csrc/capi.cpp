@@ -246,13 +246,27 @@ static PassArgs column_range(const PlanGeom& g, const PassArgs& a, int k0, int w
 // The column passes (y-forward, z, y-inverse) run best when every XCD keeps
 // the same columns for all lines and all XCDs get equal shares (measured on
 // MI355X: 20% for the y-forward pass at 512^3): the launch covers a multiple
-// of 8 x (columns per 128-byte line) columns, and the few columns left over
-// go to the narrowest variant of the same pass.
+// of 8 x (columns per 128-byte line) columns, and the columns left over get
+// a second launch (tail_variant).
+static int colpass_align(const PlanGeom& g) { return 8 * (128 / int(2 * g.elem)); }
+
+// The variant for the `rest` columns past the aligned launch: the narrowest
+// variant of the pass for a single column, the pass's own variant (its last
+// tile partly filled) for more.  The narrow variants read one value per
+// 128-byte line, so running many columns through them is slow (measured on
+// MI355X at 512^3 FP64: 13.1 ms with 96-column slabs, whose 32-column
+// remainders went to them, against 6.05 ms with 64-column slabs).
+static const PassVariant* tail_variant(const PassVariant& v, int rest) {
+  const PassVariant* nv = narrow_variant(v);
+  if (!nv) return nullptr;
+  return rest == 1 ? nv : &v;
+}
+
 void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
                      const SideStream* side) {
-  const int align = 8 * (128 / int(2 * g.elem));
-  const PassVariant* nv = narrow_variant(*v);
+  const int align = colpass_align(g);
   const int kmain = a.kx / align * align;
+  const PassVariant* nv = tail_variant(*v, a.kx - kmain);
   if (!nv || kmain == 0 || kmain == a.kx) {
     v->launch(a, ws, ws, st);
     return;
@@ -311,10 +325,12 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
     // width go through all three column passes on the side stream, beside the
     // main launches, with one fork after the x pass and one join before the
     // last one
-    const int align = 8 * (128 / int(2 * g.elem));
+    const int align = colpass_align(g);
     const int kmain = a.kx / align * align;
-    const PassVariant* nv[3] = {narrow_variant(*var[1]), narrow_variant(*var[2]), narrow_variant(*var[3])};
-    if (kmain > 0 && kmain < a.kx && nv[0] && nv[1] && nv[2]) {
+    const int rest = a.kx - kmain;
+    const PassVariant* nv[3] = {tail_variant(*var[1], rest), tail_variant(*var[2], rest),
+                                tail_variant(*var[3], rest)};
+    if (kmain > 0 && rest > 0 && nv[0] && nv[1] && nv[2]) {
       void* wm = nullptr;
       void* wr = nullptr;
       const PassArgs am = column_range(g, a, 0, kmain, work, &wm);
