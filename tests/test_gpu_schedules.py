@@ -14,7 +14,9 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_schedules_match_oracle_and_each_other(prec):
-    # nx = 250 pads to 512: 257 x-frequencies, slabs of 16/48/128 leave ragged ends
+    # nx = 250 pads to 512: 257 x-frequencies; slabs of 16/48/80/128/144 leave
+    # ragged ends, some one column and some several columns past the aligned
+    # launch width
     shape, pad = (20, 24, 250), (64, 64, 512)
     rng = np.random.default_rng(21)
     f = rng.standard_normal(shape)
@@ -26,7 +28,7 @@ def test_schedules_match_oracle_and_each_other(prec):
     fd = torch.from_numpy(f).to("cuda", dt)
     ref = oracle.solve(f, h, M=pad)
     base = None
-    for slab in (0, 16, 48, 128):
+    for slab in (0, 16, 48, 80, 128, 144):
         for side in (False, True):
             print("[case] %s slab %d side %s" % (prec, slab, side), flush=True)
             plan.slab = slab
@@ -42,6 +44,24 @@ def test_schedules_match_oracle_and_each_other(prec):
                 rel = float(np.abs(un - base).max() / np.abs(base).max())
                 assert rel <= (4e-16 if prec == "f64" else 2e-7), (slab, side, rel)
 
+
+
+@pytest.mark.parametrize("side", [False, True])
+def test_wide_column_remainder(side):
+    # nx = 190 padded to 384 (FP32): 193 x-frequencies, 65 past the aligned
+    # 128-column launch, which take a second launch of the pass's own kernel
+    shape, pad = (12, 20, 190), (32, 64, 384)
+    rng = np.random.default_rng(23)
+    f = rng.standard_normal(shape).astype(np.float32).astype(np.float64)
+    h = 1.0 / 190
+    plan = Plan(shape, h, "f32", pad=pad)
+    plan.set_side_stream(side)
+    print("[case] f32 pad 384 side %s" % side, flush=True)
+    u = plan.solve(torch.from_numpy(f).to("cuda", torch.float32))
+    torch.cuda.synchronize()
+    ref = oracle.solve(f, h, M=pad)
+    err = float(np.abs(u.double().cpu().numpy() - ref).max() / np.abs(ref).max())
+    assert err < 3e-6, err
 
 
 @pytest.mark.parametrize("prec,slab,side", [("f64", 128, True), ("f64", 0, True), ("f32", 0, False),
