@@ -175,7 +175,8 @@ int ups_plan_slab(ups_plan_t plan);
 
 /* Each column pass runs over the largest multiple of 8 x (columns per
  * 128-byte line) x-frequencies in one launch and over the remaining columns
- * in a second, narrower launch.  With one slab and `enable` != 0 the
+ * in a second launch (a one-column kernel for one column, the pass's own
+ * kernel for more); call these the narrow launches.  With one slab and `enable` != 0 the
  * narrow launches of all three column passes run on a plan-owned stream,
  * forked from the caller's stream after the x pass (FP64) or after the main
  * y-forward launch (FP32) and joined back before the inverse x pass with
