@@ -176,11 +176,12 @@ int ups_plan_slab(ups_plan_t plan);
 /* Each column pass runs over the largest multiple of 8 x (columns per
  * 128-byte line) x-frequencies in one launch and over the remaining columns
  * in a second launch (a one-column kernel for one column, the pass's own
- * kernel for more); call these the narrow launches.  With one slab and `enable` != 0 the
- * narrow launches of all three column passes run on a plan-owned stream,
- * forked from the caller's stream after the x pass (FP64) or after the main
- * y-forward launch (FP32) and joined back before the inverse x pass with
- * events (ups_run_pass forks and joins around the one pass); with several slabs `enable` != 0 pipelines them (see
+ * kernel for more); call these the narrow launches.  With one slab and
+ * `enable` != 0 the narrow launches of all three column passes run on a
+ * plan-owned stream, forked from the caller's stream after the x pass (FP64)
+ * or after the main y-forward launch (FP32) and joined back before the
+ * inverse x pass with events (ups_run_pass forks and joins around the one
+ * pass); with several slabs `enable` != 0 pipelines them (see
  * ups_plan_set_slab).  0 keeps every launch on the caller's stream.
  * Results are identical either way (the same kernels run). */
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable);
