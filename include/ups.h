@@ -28,7 +28,12 @@
  *     work completes.  The library never allocates device memory.
  *   - Execution is stream ordered (stream = hipStream_t, NULL = the legacy
  *     default stream); no call synchronises the host except ups_plan_setup,
- *     ups_batch_setup and ups_autotune.
+ *     ups_batch_setup, ups_autotune and the opt-in checks (ups_solve with
+ *     ups_plan_set_check_finite on, or in guard mode).
+ *   - One solve in flight per plan (and per batch): a plan owns one work
+ *     buffer, one side stream and one set of fork/join events, so two solves
+ *     on the same plan must not overlap.  Enqueue them on one stream, or
+ *     order them with events; use one plan per concurrently running stream.
  *   - Real arrays are C-contiguous [component][z][y][x] (x fastest), in the
  *     plan's precision (double for UPS_F64, float for UPS_F32), aligned to
  *     2 * sizeof(element) bytes.
@@ -42,7 +47,7 @@
 extern "C" {
 #endif
 
-#define UPS_ABI_VERSION 1
+#define UPS_ABI_VERSION 2
 
 typedef enum {
   UPS_OK = 0,
@@ -50,7 +55,7 @@ typedef enum {
   UPS_ERR_UNSUPPORTED = 2, /* valid problem the library does not handle */
   UPS_ERR_WORKSPACE = 3,   /* caller buffer smaller than ups_*_sizes asked */
   UPS_ERR_DEVICE = 4,      /* no usable gfx950 device, or a HIP call failed */
-  UPS_ERR_NONFINITE = 5,   /* reserved: non-finite input detected */
+  UPS_ERR_NONFINITE = 5,   /* NaN or infinite input (ups_plan_set_check_finite) */
   UPS_ERR_INTERNAL = 6,    /* library bug */
   UPS_ERR_STATE = 7        /* call out of order (e.g. solve before setup) */
 } ups_status;
@@ -130,8 +135,35 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
  * z fused with the multiply by G_hat and the inverse along z, inverse along
  * y, inverse real FFT along x fused with the crop.  f and u are real arrays
  * [ncomp][nz][ny][nx]; u may equal f (in place).  f is not modified unless
- * u == f.  Errors: STATE (setup not done), INVALID_ARG (null/misaligned). */
+ * u == f.  Errors: STATE (setup not done), INVALID_ARG (null/misaligned),
+ * NONFINITE (check on and f holds a NaN or infinity: nothing is solved),
+ * INTERNAL (guard mode found a canary band overwritten or NaN poison in the
+ * output), DEVICE (a HIP call failed).
+ *
+ * Guard mode: with the environment variable UPS_DEBUG_GUARDS set (and not
+ * "0") when the plan is created, the work buffer holds a 64 KiB canary band
+ * on each side of W (ups_plan_sizes includes them; ups_plan_work_offset
+ * gives W's offset).  ups_solve then fills W with NaN words, runs the five
+ * passes one at a time on the caller's stream (no side stream, no slabs),
+ * poisons the rows y >= ny of W again before the last pass, checks both
+ * bands after every pass and, for a finite input, checks the output for
+ * NaN.  It waits for the stream after every pass: a debugging aid for
+ * out-of-bounds stores and reads of unwritten data, not a fast path. */
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream);
+
+/* Opt-in input check (off by default): with `enable` != 0 every ups_solve
+ * on this plan first scans f for NaN and infinite values on the GPU, waits
+ * for the stream and returns UPS_ERR_NONFINITE without solving if it finds
+ * one.  The check reads f once more and synchronises the host. */
+ups_status ups_plan_set_check_finite(ups_plan_t plan, int enable);
+
+/* 1 if the plan was created in guard mode (see ups_solve), 0 if not, -1 for
+ * NULL. */
+int ups_plan_guard_mode(ups_plan_t plan);
+
+/* Byte offset of W inside the work buffer: 0, or the canary band's size in
+ * guard mode. */
+size_t ups_plan_work_offset(ups_plan_t plan);
 
 /* Adjoint of ups_solve: grad_f[j] = h^2 sum_i G1[i - j] grad_u[i].  G1 is
  * even in every index (the 7-point stencil is symmetric), so this is the
@@ -205,9 +237,10 @@ ups_status ups_plan_layout(ups_plan_t plan, int* pitch, long long* plane, long l
 double ups_plan_model_bytes(ups_plan_t plan, int pass);
 
 /* Time every compiled kernel variant of each pass, pass by pass, inside
- * whole solves on this plan's bound buffers with the current choices for
- * the other passes and the plan's schedule (HIP events on `stream`; the
- * work buffer's contents are overwritten; best of two runs of 5 solves).
+ * whole solves from the caller's f into the caller's u (arrays laid out as
+ * for ups_solve, on this plan's bound work buffer) with the current choices
+ * for the other passes and the plan's schedule (HIP events on `stream`; u
+ * and the work buffer are overwritten; best of two runs of 5 solves).
  * A variant replaces the current choice only if it is faster by more than
  * 1%.  Plans with at least 256 x-frequencies then also try one slab and
  * 128- or 256-column slabs pipelined over two streams (ups_plan_set_slab)
@@ -215,10 +248,14 @@ double ups_plan_model_bytes(ups_plan_t plan, int pass);
  * the plan only).  Candidates other than the current choice are skipped
  * once `budget_ms` of GPU time is spent.  The choices go to a process-wide
  * cache used by later plans and batches of the same (pass, precision,
- * padded length); with the environment variable UPS_TUNE_CACHE set to a
- * file path the cache is loaded from and saved to that JSON file.  Waits for
- * the stream.  Errors: STATE (setup not done), DEVICE. */
-ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms);
+ * padded length, size class), the size class being floor(log2) of the
+ * number of lines the pass transforms (rows for the x passes, kx columns
+ * times z planes for the y passes, kx times ky columns for the z pass,
+ * times ncomp); keys read "zconv/f32/1024/l19".  With the environment
+ * variable UPS_TUNE_CACHE set to a file path the cache is loaded from and
+ * saved to that JSON file.  Waits for the stream.  Errors: INVALID_ARG (null
+ * or misaligned f or u), STATE (setup not done), DEVICE. */
+ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, double budget_ms);
 
 /* Release the host-side plan.  Device buffers stay with the caller. */
 ups_status ups_plan_destroy(ups_plan_t plan);

@@ -3,7 +3,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libups.so")
+# UPS_LIB names another in-tree build of the same library (the sanitizer
+# build libups_san.so); the default is libups.so
+LIB_PATH = os.path.join(_HERE, os.path.basename(os.environ.get("UPS_LIB") or "libups.so"))
 
 UPS_OK = 0
 UPS_ERR_INVALID_ARG = 1
@@ -64,7 +66,10 @@ SIGNATURES = {
     "ups_plan_side_stream": (C.c_int, [C.c_void_p]),
     "ups_plan_model_bytes": (C.c_double, [C.c_void_p, C.c_int]),
     "ups_plan_destroy": (C.c_int, [C.c_void_p]),
-    "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    "ups_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "ups_plan_set_check_finite": (C.c_int, [C.c_void_p, C.c_int]),
+    "ups_plan_guard_mode": (C.c_int, [C.c_void_p]),
+    "ups_plan_work_offset": (C.c_size_t, [C.c_void_p]),
     "ups_batch_create": (C.c_int, [C.POINTER(ups_problem), C.c_int, C.POINTER(C.c_void_p)]),
     "ups_batch_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "ups_batch_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -1,8 +1,11 @@
-// Autotuner: per (pass, precision, padded length), time every compiled
-// kernel variant on the plan's own buffers with HIP events and keep the
-// fastest.  Choices live in a process-wide cache that new plans and batches
-// consult; with UPS_TUNE_CACHE=<path> the cache is read from and written to
-// that JSON file ({"zconv/f32/1024": "zconv_float_32x32_c8_h2", ...}).
+// Autotuner: per (pass, precision, padded length, size class), time every
+// compiled kernel variant on the plan's own buffers with HIP events and keep
+// the fastest.  The size class is floor(log2) of the number of lines the
+// pass transforms, so a tune on a thin grid does not decide for a large one
+// of the same padded length.  Choices live in a process-wide cache that new
+// plans and batches consult; with UPS_TUNE_CACHE=<path> the cache is read
+// from and written to that JSON file
+// ({"zconv/f32/1024/l19": "zconv_float_w16_c16_t", ...}).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -30,11 +33,38 @@ std::mutex g_mu;
 std::map<std::string, std::string> g_cache;
 bool g_loaded = false;
 
-std::string key_of(PassKind kind, bool f64, int length) {
+}  // namespace
+
+namespace ups {
+
+// Lines one launch of pass `kind` transforms on geometry g: rows for the x
+// passes, (kx, z) columns for the y passes, (kx, ky) columns for the z pass.
+long long pass_lines(PassKind kind, const PlanGeom& g) {
+  switch (kind) {
+    case PASS_XFWD:
+    case PASS_XINV: return (long long)g.ny * g.nz * g.ncomp;
+    case PASS_YFWD:
+    case PASS_YINV: return (long long)g.kx * g.nz * g.ncomp;
+    default: return (long long)g.kx * g.my * g.ncomp;
+  }
+}
+
+std::string tune_key(PassKind kind, const PlanGeom& g) {
+  const int length = kind == PASS_XFWD || kind == PASS_XINV ? g.mx : kind == PASS_ZCONV ? g.mz : g.my;
+  long long lines = pass_lines(kind, g);
+  int lg = 0;
+  while (lines > 1) {
+    lines >>= 1;
+    ++lg;
+  }
   char buf[64];
-  snprintf(buf, sizeof buf, "%s/%s/%d", kKindName[int(kind)], f64 ? "f64" : "f32", length);
+  snprintf(buf, sizeof buf, "%s/%s/%d/l%d", kKindName[int(kind)], g.f64 ? "f64" : "f32", length, lg);
   return buf;
 }
+
+}  // namespace ups
+
+namespace {
 
 // minimal reader for a flat {"key": "value", ...} object
 void load_locked() {
@@ -80,12 +110,12 @@ namespace ups {
 
 // The variant a new plan uses: the cached tuning result if any, else the
 // table default.
-const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom&) {
+const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom& g) {
   std::string name;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
-    auto it = g_cache.find(key_of(kind, f64, length));
+    auto it = g_cache.find(tune_key(kind, g));
     if (it != g_cache.end()) name = it->second;
   }
   if (!name.empty()) {
@@ -99,9 +129,13 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
 
 extern "C" {
 
-ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
+ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, double budget_ms) {
   if (!plan) return set_error(UPS_ERR_INVALID_ARG, "plan is NULL");
   if (!plan->ready) return set_error(UPS_ERR_STATE, "ups_plan_setup has not completed on this plan");
+  if (!f || !u) return set_error(UPS_ERR_INVALID_ARG, "f and u must be device arrays laid out as for ups_solve");
+  const uintptr_t al = 2 * plan->g.elem - 1;
+  if ((reinterpret_cast<uintptr_t>(f) | reinterpret_cast<uintptr_t>(u)) & al)
+    return set_error(UPS_ERR_INVALID_ARG, "f and u are misaligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const PlanGeom& g = plan->g;
   const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
@@ -109,21 +143,21 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return set_error(UPS_ERR_DEVICE, "hipEventCreate failed");
   // Candidates are timed inside whole solves with the current choices for
-  // the other passes and the plan's schedule: a pass's speed depends on how
-  // the pass before it left the caches (measured: timing one pass in a loop
-  // picks different, slower variants).  The work buffer stands in for f and
-  // u (timing does not depend on the values).
-  void* work = plan->work;
+  // the other passes and the plan's schedule, from the caller's f into the
+  // caller's u: a pass's speed depends on how the pass before it left the
+  // caches (measured: timing one pass in a loop picks different, slower
+  // variants), so the x passes must see the traffic of a real solve.
+  void* work = plan->wbuf();
   const SideStream* side = plan->use_side ? &plan->side : nullptr;
   double spent = 0.0;
   hipError_t err = hipSuccess;
   auto time_once = [&](float* ms_out) {
     const int reps = 5;
-    ups_status s = enqueue_solve(g, plan->var, plan->args, plan->slab, work, work, work, st, side);  // warm-up
+    ups_status s = enqueue_solve(g, plan->var, plan->args, plan->slab, f, u, work, st, side);  // warm-up
     if (s != UPS_OK) return hipErrorLaunchFailure;
     hipError_t e = hipEventRecord(e0, st);
     for (int r = 0; r < reps && e == hipSuccess; ++r)
-      if (enqueue_solve(g, plan->var, plan->args, plan->slab, work, work, work, st, side) != UPS_OK)
+      if (enqueue_solve(g, plan->var, plan->args, plan->slab, f, u, work, st, side) != UPS_OK)
         e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -164,7 +198,7 @@ ups_status ups_autotune(ups_plan_t plan, void* stream, double budget_ms) {
     plan->var[k] = best;
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
-    g_cache[key_of(kKinds[k], g.f64, len[k])] = best->name;
+    g_cache[tune_key(kKinds[k], g)] = best->name;
   }
   // then the column schedule: one slab on one or two streams, or 128- or
   // 256-column slabs pipelined over two streams (plans with at least 256

@@ -6,10 +6,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
 #include "../../include/ups.h"
+#include "debug.hpp"
 #include "green.hpp"
 #include "passes.hpp"
 #include "plan.hpp"
@@ -108,18 +110,28 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   g->gz = int(align_up(size_t(g->oz), 16));
   g->ncomp = p->ncomp;
   g->h = p->h[0];
+  // Every kernel addresses W as a wave-uniform 64-bit base plus a 32-bit
+  // per-lane byte offset of at most 64 line strides (a row of a 64-row
+  // block or of a split factor <= 64) plus a tile column; the longest line
+  // stride is the plane.  Refuse geometries where that could wrap.
+  const unsigned long long lane_max =
+      (64ull * (unsigned long long)g->my * (unsigned long long)g->px + 16ull) * (2ull * g->elem);
+  if (lane_max >= (1ull << 32))
+    return fail(UPS_ERR_UNSUPPORTED, "padded lengths (%d, %d, %d): per-lane offsets exceed 32 bits", g->mx, g->my,
+                g->mz);
   return UPS_OK;
 }
 
-void plan_layout(PlanGeom& g) {
+void plan_layout(PlanGeom& g, bool guards) {
   const size_t ce = 2 * g.elem;  // complex element
   g.plane = (long long)g.my * g.px;
   g.comp_w = (long long)g.nz * g.plane;
   g.solve_work = align_up(ce * (size_t)g.comp_w * g.ncomp, 256);
+  g.guard = guards ? kGuardBytes : 0;
   const GreenScratch gs = green_scratch_layout(g.oz, g.oy, g.kx);
   const int mmax = std::max(g.mx, std::max(g.my, g.mz));
   const size_t setup = std::max(gs.bytes, align_up(sizeof(double) * 2 * twiddle_entries(mmax), 256));
-  g.work_bytes = std::max(g.solve_work, setup);
+  g.work_bytes = std::max(g.solve_work + 2 * g.guard, setup);
   size_t off = 0;
   g.off_ghat = off;
   off = align_up(off + g.elem * (size_t)g.oy * g.kx * g.gz, 256);
@@ -129,6 +141,8 @@ void plan_layout(PlanGeom& g) {
   off = align_up(off + ce * twiddle_entries(g.my), 256);
   g.off_twz = off;
   off = align_up(off + ce * twiddle_entries(g.mz), 256);
+  g.off_status = off;
+  off += 256;
   g.green_bytes = off;
 }
 
@@ -185,11 +199,13 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
   a.gz = g.gz;
   a.g_plane = (long long)g.kx * g.gz;
   a.ncomp = g.ncomp;
-  const char* gb = static_cast<const char*>(green);
-  a.ghat = gb + g.off_ghat;
-  a.tw_x = gb + g.off_twx;
-  a.tw_y = gb + g.off_twy;
-  a.tw_z = gb + g.off_twz;
+  if (green) {  // (a geometry-only PassArgs, e.g. for block counts, has no buffers)
+    const char* gb = static_cast<const char*>(green);
+    a.ghat = gb + g.off_ghat;
+    a.tw_x = gb + g.off_twx;
+    a.tw_y = gb + g.off_twy;
+    a.tw_z = gb + g.off_twz;
+  }
   return a;
 }
 
@@ -262,30 +278,35 @@ static const PassVariant* tail_variant(const PassVariant& v, int rest) {
   return rest == 1 ? nv : &v;
 }
 
-void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
-                     const SideStream* side) {
+hipError_t enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
+                           const SideStream* side) {
   const int align = colpass_align(g);
   const int kmain = a.kx / align * align;
   const PassVariant* nv = tail_variant(*v, a.kx - kmain);
   if (!nv || kmain == 0 || kmain == a.kx) {
     v->launch(a, ws, ws, st);
-    return;
+    return hipGetLastError();
   }
   void* wm = nullptr;
   void* wr = nullptr;
   const PassArgs am = column_range(g, a, 0, kmain, ws, &wm);
   const PassArgs ar = column_range(g, a, kmain, a.kx - kmain, ws, &wr);
   if (side && side->s) {
-    hipEventRecord(side->fork, st);
-    hipStreamWaitEvent(side->s, side->fork, 0);
+    // nothing is enqueued on the side stream unless the fork is in place,
+    // and the caller's stream waits for the join before it continues
+    hipError_t e = hipEventRecord(side->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+    if (e != hipSuccess) return e;
     nv->launch(ar, wr, wr, side->s);
-    hipEventRecord(side->join, side->s);
+    e = hipEventRecord(side->join, side->s);
     v->launch(am, wm, wm, st);
-    hipStreamWaitEvent(st, side->join, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+    if (e != hipSuccess) return e;
   } else {
     v->launch(am, wm, wm, st);
     nv->launch(ar, wr, wr, st);
   }
+  return hipGetLastError();
 }
 
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
@@ -304,15 +325,15 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
     };
     for (int s = 0; s < ns; ++s) b[s] = slab_args(g, a, slab, s, work, &ws[s]);
     for (int s = 0; s < ns; ++s) {
-      enqueue_colpass(g, var[1], b[s], ws[s], st);
+      chk(enqueue_colpass(g, var[1], b[s], ws[s], st));
       chk(hipEventRecord(side->ev[2 * s], st));
       chk(hipStreamWaitEvent(side->s, side->ev[2 * s], 0));
-      enqueue_colpass(g, var[2], b[s], ws[s], side->s);
+      chk(enqueue_colpass(g, var[2], b[s], ws[s], side->s));
       chk(hipEventRecord(side->ev[2 * s + 1], side->s));
     }
     for (int s = 0; s < ns; ++s) {
       chk(hipStreamWaitEvent(st, side->ev[2 * s + 1], 0));
-      enqueue_colpass(g, var[3], b[s], ws[s], st);
+      chk(enqueue_colpass(g, var[3], b[s], ws[s], st));
     }
     var[4]->launch(a, work, u, st);
     hipError_t e = hipGetLastError();
@@ -353,15 +374,16 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
       return UPS_OK;
     }
   }
-  for (int s = 0; s < ns; ++s) {
+  hipError_t e = hipGetLastError();
+  for (int s = 0; s < ns && e == hipSuccess; ++s) {
     void* ws = nullptr;
     const PassArgs b = slab_args(g, a, slab, s, work, &ws);
-    enqueue_colpass(g, var[1], b, ws, st, side);
-    enqueue_colpass(g, var[2], b, ws, st, side);
-    enqueue_colpass(g, var[3], b, ws, st, side);
+    for (int p = 1; p <= 3 && e == hipSuccess; ++p) e = enqueue_colpass(g, var[p], b, ws, st, side);
   }
-  var[4]->launch(a, work, u, st);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    var[4]->launch(a, work, u, st);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return UPS_OK;
 }
@@ -408,7 +430,9 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   PlanGeom g{};
   ups_status s = validate_problem(prob, &g);
   if (s != UPS_OK) return s;
-  plan_layout(g);
+  const char* gv = std::getenv("UPS_DEBUG_GUARDS");
+  const bool guards = gv && *gv && std::strcmp(gv, "0") != 0;
+  plan_layout(g, guards);
   const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
   const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
   ups_plan_s* p = new ups_plan_s();
@@ -416,6 +440,7 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   p->g = g;
   p->slab = default_slab(g);
   p->use_side = default_side(g);
+  p->guards = guards;
   for (int i = 0; i < 5; ++i) {
     p->var[i] = tuned_variant(kinds[i], g.f64, len[i], g);
     if (!p->var[i]) {
@@ -455,6 +480,14 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, gb + g.off_twz, work, st);
   if (e == hipSuccess)
     e = build_green(g.f64, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
+  if (e == hipSuccess) e = enqueue_set_word(reinterpret_cast<unsigned*>(gb + g.off_status), 0u, st);
+  if (e == hipSuccess && g.guard) {
+    // canary bands below and above W (the Green's build used them as scratch)
+    char* wb = static_cast<char*>(work);
+    e = enqueue_fill_words(wb, g.guard, kCanaryWord, st);
+    if (e == hipSuccess) e = enqueue_fill_words(wb + g.guard + g.solve_work, g.guard, kCanaryWord, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "setup failed: %s", hipGetErrorString(e));
   if (!plan->side.s) {
     e = hipStreamCreateWithFlags(&plan->side.s, hipStreamNonBlocking);
@@ -482,13 +515,103 @@ static ups_status check_io(ups_plan_t plan, const void* in, const void* out) {
   return UPS_OK;
 }
 
+// Read the plan's status word into *out, waiting for the stream.
+static hipError_t read_status(ups_plan_t plan, hipStream_t st, unsigned* out) {
+  const char* gb = static_cast<const char*>(plan->green);
+  hipError_t e = hipMemcpyAsync(out, gb + plan->g.off_status, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+static unsigned* status_word(ups_plan_t plan) {
+  return reinterpret_cast<unsigned*>(static_cast<char*>(plan->green) + plan->g.off_status);
+}
+
+// Any NaN or infinity among the ncomp nx ny nz values of x?  Waits.
+static ups_status check_nonfinite(ups_plan_t plan, const void* x, hipStream_t st, bool* bad) {
+  const PlanGeom& g = plan->g;
+  const size_t n = (size_t)g.ncomp * g.nx * g.ny * g.nz;
+  unsigned* w = status_word(plan);
+  hipError_t e = enqueue_set_word(w, 0u, st);
+  if (e == hipSuccess) e = enqueue_nonfinite(g.f64, x, n, w, st);
+  unsigned v = 0;
+  if (e == hipSuccess) e = read_status(plan, st, &v);
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "non-finite check failed: %s", hipGetErrorString(e));
+  *bad = (v & kStatNonfinite) != 0;
+  return UPS_OK;
+}
+
+// Guard mode: the five passes one at a time on the caller's stream, with W
+// filled with NaN words before the first pass, the rows y >= ny of every
+// plane poisoned again before the last (pass 4 must read rows y < ny only),
+// and both canary bands checked after every pass.  Waits after every pass.
+static ups_status guarded_solve(ups_plan_t plan, const void* f, void* u, hipStream_t st) {
+  const PlanGeom& g = plan->g;
+  char* wb = static_cast<char*>(plan->work);
+  void* W = plan->wbuf();
+  unsigned* w = status_word(plan);
+  static const char* kPass[5] = {"x-forward", "y-forward", "z-convolution", "y-inverse", "x-inverse"};
+  hipError_t e = enqueue_set_word(w, 0u, st);
+  if (e == hipSuccess) e = enqueue_fill_words(W, g.solve_work, kNanWord, st);
+  for (int p = 0; p < 5 && e == hipSuccess; ++p) {
+    if (p == 4) {
+      const size_t cb = 2 * g.elem;
+      e = enqueue_poison_rows(W, (long long)g.nz * g.ncomp, size_t(g.plane) * cb, size_t(g.ny) * g.px * cb,
+                              size_t(g.my - g.ny) * g.px * cb, kNanWord, st);
+      if (e != hipSuccess) break;
+    }
+    if (p == 0) plan->var[0]->launch(plan->args, f, W, st);
+    else if (p == 4) plan->var[4]->launch(plan->args, W, u, st);
+    else e = enqueue_colpass(g, plan->var[p], plan->args, W, st, nullptr);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = enqueue_check_words(wb, g.guard, kCanaryWord, w, kStatGuardLow, st);
+    if (e == hipSuccess)
+      e = enqueue_check_words(wb + g.guard + g.solve_work, g.guard, kCanaryWord, w, kStatGuardHigh, st);
+    unsigned v = 0;
+    if (e == hipSuccess) e = read_status(plan, st, &v);
+    if (e != hipSuccess) break;
+    if (v & (kStatGuardLow | kStatGuardHigh))
+      return fail(UPS_ERR_INTERNAL, "guard mode: the canary band %s the work buffer was overwritten by the %s pass",
+                  (v & kStatGuardLow) ? "below" : "above", kPass[p]);
+  }
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "guarded solve: %s", hipGetErrorString(e));
+  return UPS_OK;
+}
+
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   ups_status s = check_io(plan, f, u);
   if (s != UPS_OK) return s;
-  s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->work, static_cast<hipStream_t>(stream),
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool bad = false;
+  if (plan->check_finite || plan->guards) {
+    s = check_nonfinite(plan, f, st, &bad);
+    if (s != UPS_OK) return s;
+    if (bad && plan->check_finite)
+      return fail(UPS_ERR_NONFINITE, "the input holds NaN or infinite values; nothing was solved");
+  }
+  if (plan->guards) {
+    s = guarded_solve(plan, f, u, st);
+    if (s != UPS_OK) return s;
+    // NaN poison in the output of a finite input: a pass read work-buffer
+    // data that no earlier pass wrote
+    bool ubad = false;
+    if (!bad) s = check_nonfinite(plan, u, st, &ubad);
+    if (s != UPS_OK) return s;
+    if (ubad) return fail(UPS_ERR_INTERNAL, "guard mode: NaN poison reached the output of a finite input");
+    return ok();
+  }
+  s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->wbuf(), st,
                     plan->use_side ? &plan->side : nullptr);
   return s == UPS_OK ? ok() : s;
 }
+
+ups_status ups_plan_set_check_finite(ups_plan_t plan, int enable) {
+  if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
+  plan->check_finite = enable != 0;
+  return ok();
+}
+
+int ups_plan_guard_mode(ups_plan_t plan) { return plan ? (plan->guards ? 1 : 0) : -1; }
 
 ups_status ups_solve_adjoint(ups_plan_t plan, const void* grad_u, void* grad_f, void* stream) {
   // K^T = K: G1[i - j] = G1[j - i] for the symmetric 7-point stencil.
@@ -497,16 +620,19 @@ ups_status ups_solve_adjoint(ups_plan_t plan, const void* grad_u, void* grad_f, 
 
 ups_status ups_run_pass(ups_plan_t plan, int pass, const void* in, void* out, void* stream) {
   if (pass < 0 || pass > 4) return fail(UPS_ERR_INVALID_ARG, "pass %d not in 0..4", pass);
-  const void* i = pass == 0 ? in : plan ? plan->work : nullptr;
-  void* o = pass == 4 ? out : plan ? plan->work : nullptr;
+  if (plan && !plan->ready) return fail(UPS_ERR_STATE, "ups_plan_setup has not completed on this plan");
+  const void* i = pass == 0 ? in : plan ? plan->wbuf() : nullptr;
+  void* o = pass == 4 ? out : plan ? plan->wbuf() : nullptr;
   ups_status s = check_io(plan, i, o);
   if (s != UPS_OK) return s;
-  if (pass >= 1 && pass <= 3)
-    enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream),
-                    plan->use_side ? &plan->side : nullptr);
-  else
+  hipError_t e = hipSuccess;
+  if (pass >= 1 && pass <= 3) {
+    e = enqueue_colpass(plan->g, plan->var[pass], plan->args, o, static_cast<hipStream_t>(stream),
+                        plan->use_side ? &plan->side : nullptr);
+  } else {
     plan->var[pass]->launch(plan->args, i, o, static_cast<hipStream_t>(stream));
-  hipError_t e = hipGetLastError();
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return ok();
 }
@@ -566,6 +692,8 @@ ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable) {
 }
 
 int ups_plan_side_stream(ups_plan_t plan) { return plan ? (plan->use_side ? 1 : 0) : -1; }
+
+size_t ups_plan_work_offset(ups_plan_t plan) { return plan ? plan->g.guard : 0; }
 
 double ups_plan_model_bytes(ups_plan_t plan, int pass) {
   if (!plan || pass < -1 || pass > 4) return 0.0;

@@ -19,13 +19,16 @@ struct PlanGeom {
   double h;
   long long plane, comp_w;   // W strides (complex elements)
   size_t solve_work;         // bytes of W
-  size_t work_bytes;         // max(W, setup scratch)
+  size_t guard;              // bytes of each canary band around W (guard mode), else 0
+  size_t work_bytes;         // max(guard + W + guard, setup scratch)
   size_t green_bytes;
   size_t off_ghat, off_twx, off_twy, off_twz;
+  size_t off_status;         // one status word of the debug checks (green buffer)
 };
 
 ups_status validate_problem(const ups_problem* p, PlanGeom* g);
-void plan_layout(PlanGeom& g);
+// guards: lay out canary bands around W in the work buffer (guard mode)
+void plan_layout(PlanGeom& g, bool guards = false);
 double model_bytes(const PlanGeom& g, int pass);
 const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name);
 const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom& g);
@@ -48,8 +51,8 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
                          const void* f, void* u, void* work, hipStream_t st, const SideStream* side);
 int default_slab(const PlanGeom& g);
 bool default_side(const PlanGeom& g);
-void enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
-                     const SideStream* side = nullptr);
+hipError_t enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassArgs& a, void* ws, hipStream_t st,
+                           const SideStream* side = nullptr);
 int slab_count(const PlanGeom& g, int slab);
 PassArgs slab_args(const PlanGeom& g, const PassArgs& a, int slab, int s, void* work, void** wslab);
 
@@ -67,5 +70,9 @@ struct ups_plan_s {
   ups::PassArgs args{};
   ups::SideStream side;
   bool use_side = false;     // remainder launches on the side stream
+  bool check_finite = false; // ups_solve first checks its input for NaN / Inf
+  bool guards = false;       // guard mode (UPS_DEBUG_GUARDS): canary bands, NaN poison
+  // the solve's W: the work buffer, past the low canary band in guard mode
+  void* wbuf() const { return static_cast<char*>(work) + g.guard; }
   ~ups_plan_s();
 };

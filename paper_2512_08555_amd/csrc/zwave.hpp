@@ -318,12 +318,16 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
       tslot[tr + 64 * i] = ld[i];
     });
   } else {
+    // rows >= nz are the zero padding: not loaded.  The 64-row block goes
+    // into the 64-bit base as in the full case, so the per-lane offset stays
+    // below 64 planes (a row index times the plane in 32 bits would wrap
+    // for FP64 lines of 1024 with 1024 x 528 planes).
     static_for<0, E / 2>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
       const int row = tr + 64 * i;
-      const int rowc = row < nz ? row : nz - 1;  // clamped: loads stay in bounds
-      const cx<T> val = ld_at<nt_load<2>()>(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB);
-      tslot[row] = row < nz ? val : zero_c<T>();
+      cx<T> val = zero_c<T>();
+      if (row < nz) val = ld_at<nt_load<2>()>(ubase + (long long)(64 * i) * a.plane, toff);
+      tslot[row] = val;
     });
   }
   __syncthreads();
@@ -359,12 +363,9 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
         st_at<nt_store<2>()>(ubase + (long long)(64 * i) * a.plane, toff, tslot[tr + 64 * i]);
       });
     } else {
-      // rows >= nz write row nz - 1 again (the same value): no per-row branch
       static_for<0, E / 2>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        const int row = tr + 64 * i;
-        const int rowc = row < nz ? row : nz - 1;
-        st_at<nt_store<2>()>(ubase, (unsigned(rowc) * unsigned(a.plane) + unsigned(tcl)) * CB, tslot[rowc]);
+        if (tr + 64 * i < nz) st_at<nt_store<2>()>(ubase + (long long)(64 * i) * a.plane, toff, tslot[tr + 64 * i]);
       });
     }
   }

@@ -114,10 +114,23 @@ class Plan:
         return r
 
     def run_pass(self, k, f=None, u=None, stream=None):
-        """Enqueue pass k (0..4) alone on the bound work buffer."""
-        fi = C.c_void_p(f.data_ptr()) if f is not None else C.c_void_p(self.work.data_ptr())
-        uo = C.c_void_p(u.data_ptr()) if u is not None else C.c_void_p(self.work.data_ptr())
+        """Enqueue pass k (0..4) alone on the bound work buffer (pass 0 reads f,
+        pass 4 writes u)."""
+        if (k == 0 and f is None) or (k == 4 and u is None):
+            raise ValueError("pass 0 needs f and pass 4 needs u")
+        fi = C.c_void_p(f.data_ptr()) if f is not None else C.c_void_p(None)
+        uo = C.c_void_p(u.data_ptr()) if u is not None else C.c_void_p(None)
         capi.check(capi.lib().ups_run_pass(self._h, int(k), fi, uo, _stream_handle(stream)))
+
+    def set_check_finite(self, enable=True):
+        """Scan every input for NaN / Inf before solving (UpsError
+        UPS_ERR_NONFINITE if one is found); off by default."""
+        capi.check(capi.lib().ups_plan_set_check_finite(self._h, int(bool(enable))))
+
+    @property
+    def guard_mode(self):
+        """Whether the plan was created with UPS_DEBUG_GUARDS set."""
+        return capi.lib().ups_plan_guard_mode(self._h) == 1
 
     # -- introspection ---------------------------------------------------------
     def layout(self):
@@ -187,7 +200,8 @@ class Plan:
         nz = self.shape[0]
         n = self.ncomp * lay["comp_stride"]
         esz = 16 if self.prec == "f64" else 8
-        w = self.work[: n * esz].view(ct)
+        off = capi.lib().ups_plan_work_offset(self._h)
+        w = self.work[off: off + n * esz].view(ct)
         my = lay["plane"] // lay["pitch"]
         return w.view(self.ncomp, nz, my, lay["pitch"])
 
@@ -210,10 +224,18 @@ def solve(f, h, prec=None, pad=None):
     return Plan(shape, h, prec, ncomp=ncomp, pad=pad).solve(f.contiguous())
 
 
-def _plan_autotune(self, budget_ms=200.0, stream=None):
-    """Time every compiled variant of each pass on this plan (ups_autotune)
-    and keep the fastest; returns the chosen kernel names."""
-    capi.check(capi.lib().ups_autotune(self._h, _stream_handle(stream), float(budget_ms)))
+def _plan_autotune(self, budget_ms=200.0, f=None, stream=None):
+    """Time every compiled variant of each pass on this plan (ups_autotune),
+    solving from f (a random source of the plan's shape if None) into a
+    separate output array, and keep the fastest; returns the chosen kernel
+    names."""
+    if f is None:
+        g = torch.Generator(device=self.work.device).manual_seed(0)
+        f = torch.randn(self._shape_io(), dtype=self.dtype, device=self.work.device, generator=g)
+    self._check(f, "f")
+    u = self.empty_like_io()
+    capi.check(capi.lib().ups_autotune(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                       _stream_handle(stream), float(budget_ms)))
     return [self.kernel(k) for k in range(5)]
 
 

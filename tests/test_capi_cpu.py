@@ -35,7 +35,7 @@ def test_header_symbols_exported():
 
 def test_abi_version_and_lengths():
     L = _lib_or_skip()
-    assert L.ups_abi_version() == 1
+    assert L.ups_abi_version() == 2
     for m in (32, 64, 128, 256, 512, 1024):
         assert L.ups_supported_length(m, capi.UPS_F64) == 1
         assert L.ups_supported_length(m, capi.UPS_F32) == 1
@@ -185,9 +185,95 @@ def test_autotune_requires_setup():
     p = make_problem((32, 32, 32), 1 / 32)
     s, h, _ = _create(p)
     assert s == capi.UPS_OK
-    assert L.ups_autotune(h, None, 10.0) == capi.UPS_ERR_STATE
-    assert L.ups_autotune(None, None, 10.0) == capi.UPS_ERR_INVALID_ARG
+    f, u = C.c_void_p(4096), C.c_void_p(8192)
+    assert L.ups_autotune(h, f, u, None, 10.0) == capi.UPS_ERR_STATE
+    assert L.ups_autotune(None, f, u, None, 10.0) == capi.UPS_ERR_INVALID_ARG
     L.ups_plan_destroy(h)
+
+
+def test_debug_switches_without_device():
+    L = _lib_or_skip()
+    p = make_problem((32, 32, 32), 1 / 32)
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    assert L.ups_plan_set_check_finite(h, 1) == capi.UPS_OK
+    assert L.ups_plan_set_check_finite(None, 1) == capi.UPS_ERR_INVALID_ARG
+    assert L.ups_plan_guard_mode(h) in (0, 1)
+    assert L.ups_plan_guard_mode(None) == -1
+    L.ups_plan_destroy(h)
+
+
+_GUARD_SCRIPT = r"""
+import ctypes as C, sys
+sys.path.insert(0, %r)
+from paper_2512_08555_amd import _capi as capi
+from paper_2512_08555_amd.solver import make_problem
+L = capi.lib()
+p = make_problem((32, 32, 32), 1 / 32, prec="f32")
+h = C.c_void_p()
+assert L.ups_plan_create(C.byref(p), C.byref(h)) == 0
+g, w = C.c_size_t(), C.c_size_t()
+L.ups_plan_sizes(h, C.byref(g), C.byref(w))
+print(L.ups_plan_guard_mode(h), L.ups_plan_work_offset(h), w.value)
+"""
+
+
+def _run(env_extra, script):
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    env.update(env_extra)
+    r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return r.stdout.split()
+
+
+def test_guard_mode_layout():
+    """UPS_DEBUG_GUARDS at plan creation: W moves past a 64 KiB canary band
+    and the work buffer grows by two bands."""
+    _lib_or_skip()
+    off = _run({"UPS_DEBUG_GUARDS": "0"}, _GUARD_SCRIPT % ROOT)
+    on = _run({"UPS_DEBUG_GUARDS": "1"}, _GUARD_SCRIPT % ROOT)
+    assert off[:2] == ["0", "0"] and on[:2] == ["1", str(64 * 1024)]
+    # 32^3 FP32: W = 32 * 64 * 48 complex floats; setup scratch may be larger
+    W = 32 * 64 * 48 * 8
+    assert int(on[2]) >= W + 2 * 64 * 1024
+
+
+_KEY_SCRIPT = r"""
+import ctypes as C, sys
+sys.path.insert(0, %r)
+from paper_2512_08555_amd import _capi as capi
+from paper_2512_08555_amd.solver import make_problem
+L = capi.lib()
+out = []
+for shape, pad in (((512, 512, 512), None), ((512, 16, 16), (1024, 32, 32))):
+    p = make_problem(shape, 1 / 512, prec="f32", pad=pad)
+    h = C.c_void_p()
+    assert L.ups_plan_create(C.byref(p), C.byref(h)) == 0
+    out.append(L.ups_plan_kernel(h, 2).decode())
+    L.ups_plan_destroy(h)
+print(" ".join(out))
+"""
+
+
+def test_tuning_cache_key_has_size_class(tmp_path):
+    """A cached choice applies to plans of the same pass, precision, padded
+    length and size class (floor log2 of the lines of the pass): the 512^3
+    z pass has 513 x 1024 lines (class 19); a 16 x 16 x 512 grid padded to
+    32 x 32 x 1024 has 17 x 32 (class 9) and keeps the table default."""
+    _lib_or_skip()
+    from paper_2512_08555_amd.solver import kernel_variants
+    names = kernel_variants(2, "f32", 1024)
+    default, other = names[0], names[-1]
+    assert default != other
+    cache = tmp_path / "tune.json"
+    cache.write_text('{"zconv/f32/1024/l19": "%s"}' % other)
+    got = _run({"UPS_TUNE_CACHE": str(cache)}, _KEY_SCRIPT % ROOT)
+    assert got == [other, default]
+    cache.write_text('{"zconv/f32/1024/l9": "%s"}' % other)
+    got = _run({"UPS_TUNE_CACHE": str(cache)}, _KEY_SCRIPT % ROOT)
+    assert got == [default, other]
 
 
 def test_kernel_variant_listing():

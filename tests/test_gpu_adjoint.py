@@ -84,4 +84,5 @@ def test_c5_fp32_gradient_vs_fp64_oracle():
     lref = float(grad_energy(torch.from_numpy(u), torch.from_numpy(wh), h))
     print("c5 fp32 grad rel Linf %.3e rel L2 %.3e loss rel err %.3e"
           % (linf, l2, abs(float(L) - lref) / abs(lref)), flush=True)
-    assert linf < 1e-4 and l2 < 1e-5
+    # measured 6.1e-7 and 3.3e-7: about 8x and 6x headroom
+    assert linf < 5e-6 and l2 < 2e-6

@@ -89,8 +89,9 @@ def test_batch_equals_single_plans_and_oracle():
 
 def test_batch_c4_workload_smoke():
     """The uneven-size workload (48 solves of 32..192 points per axis plus a
-    3-component 128^3 curl source) runs and matches single-plan solves on a
-    sample of its problems."""
+    3-component 128^3 curl source): every problem against the FP64 oracle
+    (every component of the vector source), and a sample bitwise against
+    single-plan solves."""
     from paper_2512_08555_amd.solver import Batch, Plan
     cfg = workloads.config_c4()
     specs = [dict(shape=p["shape"], h=p["h"], prec="f32") for p in cfg["scalar"]]
@@ -104,14 +105,16 @@ def test_batch_c4_workload_smoke():
         sp = b.specs[i]
         p = Plan(sp["shape"], sp["h"], "f32", ncomp=sp["ncomp"], pad=sp["pad"])
         assert torch.equal(p.solve(fs[i]), us[i])
-    for i in (3, 48):
-        sp = b.specs[i]
+    worst = 0.0
+    for i, sp in enumerate(b.specs):
         f = fs[i].double().cpu().numpy()
         got = us[i].double().cpu().numpy()
-        if sp["ncomp"] == 1:
-            assert _rel_inf(got, oracle.solve(f, sp["h"], M=sp["pad"])) < 3e-6
-        else:
-            assert _rel_inf(got[1], oracle.solve(f[1], sp["h"], M=sp["pad"])) < 3e-6
+        comps = [(got, f)] if sp["ncomp"] == 1 else [(got[c], f[c]) for c in range(sp["ncomp"])]
+        for g, fc in comps:
+            err = _rel_inf(g, oracle.solve(fc, sp["h"], M=sp["pad"]))
+            worst = max(worst, err)
+            assert err < 3e-6, "problem %d %s: rel Linf %.3e" % (i, sp["shape"], err)
+    print("c4: worst rel Linf over 49 problems %.3e" % worst, flush=True)
 
 
 def test_autotune_keeps_results_correct(tmp_path, monkeypatch):

@@ -57,7 +57,8 @@ def test_c3_512_f32_full_field_and_samples():
     linf = _rel_inf(u, ref)
     l2 = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
     print("c3 f32 rel Linf %.3e rel L2 %.3e" % (linf, l2), flush=True)
-    assert linf < 2e-6 and l2 < 1e-6
+    # measured 3.6e-7 and 1.9e-7: about 3x headroom, no more
+    assert linf < 1e-6 and l2 < 5e-7
     # sampled outputs against the defining lattice sum, evaluated one by one
     # on a 64^3 corner sub-problem (same kernel, same precision path)
     sub = fd[:64, :64, :64].copy()
@@ -104,3 +105,40 @@ def test_zero_input_and_delta_source():
     G1 = oracle.lgf_table(n, n, n)
     ref = h * h * G1[np.ix_(np.abs(i - c[0]), np.abs(i - c[1]), np.abs(i - c[2]))]
     assert np.abs(u - ref).max() < 1e-14
+
+
+def test_c3_source_512_f64_full_field():
+    """The 512^3 FP64 solve the bench times (the two-stream 128-column slab
+    schedule, W above 4 GiB) against the oracle over the whole field."""
+    cfg = workloads.config_c3()
+    _announce("c3 source 512^3 f64 full field, default schedule")
+    f, h = cfg["f"], cfg["h"]
+    plan = _plan(cfg["shape"], h, "f64")
+    assert plan.padded == (1024, 1024, 1024) and plan.slab == 128 and plan.side_stream
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    ref = oracle.solve(f, h)
+    print("oracle 512^3: %.1f s" % (time.time() - t0), flush=True)
+    err = _rel_inf(u, ref)
+    print("c3 source f64 rel Linf %.3e" % err, flush=True)
+    assert err < 1e-12
+
+
+def test_ragged_z_f64_at_1024_rows_past_2_32_bytes():
+    """nz = 500 < 512 takes the ragged tile path of the z pass; with FP64
+    lines of 1024 and 1024 x 528 planes, row 497 onwards lies more than 4 GiB
+    past a column's first row.  Whole field against the oracle."""
+    _announce("ragged z f64 (500, 260, 260) pad 1024^3")
+    shape, pad = (500, 260, 260), (1024, 1024, 1024)
+    h = 1.0 / 500
+    f = workloads.blob_source(shape, h, seed=12, nblobs=16, sigma=(0.02, 0.1), noise=1e-3)
+    plan = _plan(shape, h, "f64", pad=pad)
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    ref = oracle.solve(f, h, M=pad)
+    err = _rel_inf(u, ref)
+    print("ragged z f64 rel Linf %.3e" % err, flush=True)
+    assert err < 1e-12

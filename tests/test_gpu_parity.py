@@ -45,6 +45,23 @@ def test_green_spectrum_matches_oracle(shape, prec):
     assert _rel_inf(got, ref) < tol
 
 
+def test_green_spectrum_513_octant_f64():
+    """The FP64 spectrum of the 512^3 solve: the whole 513^3 octant against
+    the oracle's DCT-I of its LGF table."""
+    _announce("ghat 513^3 octant f64")
+    n = 512
+    h = 1.0 / n
+    plan = _plan((n, n, n), h, "f64")
+    got = plan.ghat().cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    ref = oracle.green_spectrum_scaled((2 * n,) * 3, h)
+    assert got.shape == ref.shape == (n + 1,) * 3
+    err = _rel_inf(got, ref)
+    print("ghat 513^3 rel Linf %.3e" % err, flush=True)
+    assert err < 1e-13
+
+
 # ---- single passes against numpy's FFT -----------------------------------------
 
 def test_passes_one_by_one_f64():
