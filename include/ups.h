@@ -25,7 +25,9 @@
  *     leaves no partial work on the stream.
  *   - Device pointers are HIP device addresses on the current device; the
  *     caller owns all device memory and keeps it alive until the enqueued
- *     work completes.  The library never allocates device memory.
+ *     work completes.  The library never allocates device memory; the one
+ *     device array it owns (UPS_NOALLOC_MAX_WORK bytes per device, used only
+ *     by ups_solve_noalloc) is reserved when its code object loads.
  *   - Execution is stream ordered (stream = hipStream_t, NULL = the legacy
  *     default stream); no call synchronises the host except ups_plan_setup,
  *     ups_batch_setup, ups_autotune and the opt-in checks (ups_solve with
@@ -150,6 +152,28 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
  * NaN.  It waits for the stream after every pass: a debugging aid for
  * out-of-bounds stores and reads of unwritten data, not a fast path. */
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream);
+
+/* Maximum bytes of W (2 x element size x ncomp x nz x my x the row pitch of
+ * ups_plan_layout, rounded up to 256) that ups_solve_noalloc handles. */
+#define UPS_NOALLOC_MAX_WORK (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ups_solve with W
+ * in a library-owned device array of UPS_NOALLOC_MAX_WORK bytes instead of
+ * the plan's work buffer.  The plan must have been set up (its green buffer
+ * holds G_hat and the twiddle tables; its work buffer is not touched by this
+ * call), on the device that is current.  The call allocates nothing: the
+ * array is one per device, reserved when the library's code object loads
+ * on that device and held until the process ends, and its address is looked
+ * up once per device.  Every call on a device shares that device's array,
+ * which keeps the last call's contents (no pass reads W before another pass
+ * of the same solve has written it, so nothing is cleared): solves through
+ * this call that overlap on one device, on any streams or plans, race, and
+ * must be ordered by the caller.  Same layout, results and errors as
+ * ups_solve, plus UNSUPPORTED (W larger than UPS_NOALLOC_MAX_WORK, or a
+ * guard-mode plan) and INVALID_ARG (another device current than the
+ * plan's). */
+ups_status ups_solve_noalloc(ups_plan_t plan, const void* f, void* u, void* stream);
 
 /* Opt-in input check (off by default): with `enable` != 0 every ups_solve
  * on this plan first scans f for NaN and infinite values on the GPU, waits

@@ -22,6 +22,7 @@ UPS_BC_UNB, UPS_BC_PER, UPS_BC_EVEN, UPS_BC_ODD = 0, 1, 2, 3
 UPS_GREEN_LGF2, UPS_GREEN_LGF4_MEHR, UPS_GREEN_LGF6_MEHR = 0, 1, 2
 UPS_F64, UPS_F32 = 0, 1
 UPS_CELL, UPS_NODE = 0, 1
+UPS_NOALLOC_MAX_WORK = 64 << 20
 
 
 class ups_problem(C.Structure):
@@ -53,6 +54,7 @@ SIGNATURES = {
     "ups_plan_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "ups_plan_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
     "ups_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ups_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ups_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ups_plan_kernel": (C.c_char_p, [C.c_void_p, C.c_int]),
     "ups_plan_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),

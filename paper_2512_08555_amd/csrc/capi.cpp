@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/ups.h"
@@ -602,6 +603,60 @@ ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   }
   s = enqueue_solve(plan->g, plan->var, plan->args, plan->slab, f, u, plan->wbuf(), st,
                     plan->use_side ? &plan->side : nullptr);
+  return s == UPS_OK ? ok() : s;
+}
+
+// ---- allocation-free solve ---------------------------------------------------
+// W of ups_solve_noalloc: one array per device in the library's own device
+// memory, held from when the code object loads on a device until the process
+// ends.  Its name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[UPS_NOALLOC_MAX_WORK];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, which must be the current device.
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+ups_status ups_solve_noalloc(ups_plan_t plan, const void* f, void* u, void* stream) {
+  ups_status s = check_io(plan, f, u);
+  if (s != UPS_OK) return s;
+  const PlanGeom& g = plan->g;
+  if (plan->guards)
+    return fail(UPS_ERR_UNSUPPORTED, "guard mode needs the canary bands of the plan's work buffer; use ups_solve");
+  if (g.solve_work > size_t(UPS_NOALLOC_MAX_WORK))
+    return fail(UPS_ERR_UNSUPPORTED, "the plan's W takes %zu bytes; ups_solve_noalloc holds at most %zu",
+                g.solve_work, size_t(UPS_NOALLOC_MAX_WORK));
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(UPS_ERR_DEVICE, "hipGetDevice failed");
+  if (cur != plan->device)
+    return fail(UPS_ERR_INVALID_ARG, "the plan was set up on device %d; device %d is current", plan->device, cur);
+  if (cur < 0 || cur >= kMaxDevices) return fail(UPS_ERR_DEVICE, "device %d out of range", cur);
+  void* W = nullptr;
+  hipError_t e = scratch_address(cur, &W);
+  if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "hipGetSymbolAddress: %s", hipGetErrorString(e));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->check_finite) {
+    bool bad = false;
+    s = check_nonfinite(plan, f, st, &bad);
+    if (s != UPS_OK) return s;
+    if (bad) return fail(UPS_ERR_NONFINITE, "the input holds NaN or infinite values; nothing was solved");
+  }
+  s = enqueue_solve(g, plan->var, plan->args, plan->slab, f, u, W, st, plan->use_side ? &plan->side : nullptr);
   return s == UPS_OK ? ok() : s;
 }
 

@@ -104,6 +104,17 @@ class Plan:
                                         _stream_handle(stream)))
         return u
 
+    def solve_noalloc(self, f, out=None, stream=None):
+        """u = h^2 G1 * f through ups_solve_noalloc: W in the library's own
+        per-device array instead of the plan's work buffer (plans whose W
+        fits in UPS_NOALLOC_MAX_WORK bytes)."""
+        self._check(f, "f")
+        u = self.empty_like_io() if out is None else out
+        self._check(u, "out")
+        capi.check(capi.lib().ups_solve_noalloc(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                                _stream_handle(stream)))
+        return u
+
     def adjoint(self, g, out=None, stream=None):
         """grad_f = K^T grad_u through ups_solve_adjoint."""
         self._check(g, "grad_u")

@@ -131,6 +131,8 @@ def test_calls_before_setup_and_without_device_fail_cleanly():
     assert s == capi.UPS_OK
     assert L.ups_solve(h, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
     assert L.ups_solve_adjoint(h, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
+    assert L.ups_solve_noalloc(h, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
+    assert L.ups_solve_noalloc(None, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_INVALID_ARG
     assert L.ups_run_pass(h, 0, C.c_void_p(4096), C.c_void_p(8192), None) == capi.UPS_ERR_STATE
     assert L.ups_run_pass(h, 9, None, None, None) == capi.UPS_ERR_INVALID_ARG
     g, w = C.c_size_t(), C.c_size_t()
