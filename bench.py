@@ -43,8 +43,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_name, model_bytes):
-    """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE +
+def load_traffic(kernel_name, model_bytes, share=1.0):
+    """HBM bytes per main launch measured by rocprofv3 counters (FETCH_SIZE +
     WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
     profile matches the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -56,7 +56,9 @@ def load_traffic(kernel_name, model_bytes):
     ent = rec.get("kernels", {}).get(kernel_name)
     if not ent or rec.get("source_hash") != kernel_source_hash():
         return None
-    return float(ent["bytes_per_launch"])
+    if "main_launch_bytes" in ent:
+        return float(ent["main_launch_bytes"])
+    return float(ent["bytes_per_launch"]) * share
 
 
 def time_passes(plan, f, u, steps, warmup):
@@ -109,28 +111,30 @@ def time_solve(plan, f, u, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(n_sample=256):
-    """The CPU oracle (scipy.fft, FP64, up to 16 host threads) on a bounded
-    sample: repeated n_sample^3 solves of the same source recipe (about 10 s
-    of CPU work); G_hat precomputed."""
+def cpu_baseline(n_sample=512, budget_s=10.0, max_reps=8):
+    """The CPU oracle (scipy.fft, FP64) on a bounded sample of the headline
+    workload: whole n_sample^3 solves of the same source recipe, repeated
+    until about `budget_s` of CPU work (G_hat precomputed, outside the timed
+    region).  Threads: the host's CPUs available to this process, at most 16
+    (the CPU share of one GPU on the measurement hosts)."""
     import oracle
     from paper_2512_08555_amd import workloads
-    workers = len(os.sched_getaffinity(0))
-    workers = min(workers, 16)
+    visible = len(os.sched_getaffinity(0))
+    workers = min(visible, 16)
     h = 1.0 / n_sample
     f = workloads.config_blobs_noise(n_sample, 2)
     M = (2 * n_sample,) * 3
     G = oracle.green_spectrum_raw(M)
-    # repeat the solve until about 10 s of CPU work (at most 40 solves)
     reps, dt = 0, 0.0
-    while reps < 40 and (dt < 10.0 or reps < 1):
+    while reps < max_reps and (dt < budget_s or reps < 1):
         t0 = time.perf_counter()
         oracle.solve(f, h, G_hat_raw=G, workers=workers)
         dt += time.perf_counter() - t0
         reps += 1
-    return {"value": reps * n_sample ** 3 / dt, "unit": "grid points/s", "cores": workers, "kind": "oracle",
-            "sample": "%d solves of the %d^3 FP64 source by oracle.solve (pruned scipy.fft, %d workers), "
-                      "G_hat precomputed; %.1f s" % (reps, n_sample, workers, dt)}
+    return {"value": reps * n_sample ** 3 / dt, "unit": "grid points/s", "cores": workers,
+            "host_cpus_visible": visible, "kind": "oracle",
+            "sample": "%d whole solves of the %d^3 FP64 blob-plus-noise source by oracle.solve (pruned "
+                      "scipy.fft, %d threads), G_hat precomputed; %.1f s" % (reps, n_sample, workers, dt)}
 
 
 def batch_leg(reps=10):
@@ -168,8 +172,26 @@ def batch_leg(reps=10):
 
     graph_ms = timed(lambda: b.solve(fs, us))
     loop_ms = timed(lambda: [p.solve(f, out=u) for p, f, u in zip(plans, fs, us)])
+    # algorithmic HBM bytes of the whole batch: each problem's five-pass model
+    # at its own padded lengths
+    model = float(sum(p.model_bytes(-1) for p in plans))
+    del plans
+    torch.cuda.empty_cache()
+    # the plain FP64 GPU path on the same problems: one FP64 plan per problem
+    # (lengths padded to the FP64 kernels' sizes), solved one after another
+    from paper_2512_08555_amd.lengths import auto_pad
+    p64 = [Plan(sp["shape"], sp["h"], "f64", ncomp=sp["ncomp"], pad=auto_pad(sp["shape"], "f64"))
+           for sp in b.specs]
+    f64s = [f.double() for f in fs]
+    u64s = [torch.empty_like(f) for f in f64s]
+    loop64_ms = timed(lambda: [p.solve(f, out=u) for p, f, u in zip(p64, f64s, u64s)])
+    worst = max(float((u.double() - r).abs().max() / r.abs().max()) for u, r in zip(us, u64s))
+    gbs = model / (graph_ms * 1e-3) / 1e9
     return {"problems": len(specs), "points": pts, "graph_ms": graph_ms, "loop_ms": loop_ms,
             "graph_pts_per_s": pts / (graph_ms * 1e-3), "batched_speedup_over_loop": loop_ms / graph_ms,
+            "f64_loop_ms": loop64_ms, "batched_speedup_over_f64_loop": loop64_ms / graph_ms,
+            "rel_linf_vs_f64_worst": worst,
+            "model_bytes": model, "hbm_gbs_model": gbs, "frac": gbs / HBM_PEAK_GBS,
             "launches_per_pass": b.launches(), "setup_ms": setup_ms}
 
 
@@ -273,17 +295,30 @@ def main():
     value = n ** 3 / (step_ms * 1e-3)
     dom = int(np.argmax(per_pass))
     dom_name = plan.kernel(dom)
-    dom_bytes = plan.model_bytes(dom)
+    # A column pass (1-3) runs one main launch over the first kmain of the kx
+    # x-frequency columns (a multiple of 8 XCDs x the columns of one 128-byte
+    # line) and a narrow launch over the rest on the plan's second stream,
+    # alongside it; the events around the pass on the caller's stream
+    # therefore time the main launch.  Every term of a column pass's byte
+    # model is linear in the number of columns, so the main launch's
+    # algorithmic bytes are the pass's times kmain / kx.
+    m = 2 * n
+    kx = m // 2 + 1
+    align = 8 * (128 // 8)   # 8 XCDs x 16 complex floats per 128-byte line
+    kzm = kx // align * align
+    kmain = kzm if dom in (1, 2, 3) else kx
+    dom_bytes = plan.model_bytes(dom) * kmain / kx
     achieved = dom_bytes / (per_pass[dom] * 1e-3) / 1e9
     # The z pass is bound by vector-ALU issue rather than by HBM: its roofline
-    # against the FP32 vector peak without packed math, with the standard FFT
-    # flop count 5 M log2 M per transform (forward and inverse) plus 2 M for
-    # the real G_hat scaling, per line (kx * my lines).
-    m = 2 * n
-    kxl = m // 2 + 1
-    z_flops = kxl * m * (2 * 5.0 * m * np.log2(m) + 2.0 * m)
+    # against the FP32 vector peak without packed math.  Flops per line of the
+    # main launch (kmain * m lines), radix-2 count of the pruned transforms:
+    # forward 5 m log2 m - 2 m (the first layer's partners are the zero
+    # padding: one complex product per pair instead of a butterfly), inverse
+    # 5 m log2 m - m (the last layer keeps half its outputs), plus 2 m for
+    # the real G_hat scaling.
+    z_flops = kzm * m * ((5.0 * m * np.log2(m) - 2.0 * m) + (5.0 * m * np.log2(m) - m) + 2.0 * m)
     z_tflops = z_flops / (per_pass[2] * 1e-3) / 1e12
-    traffic = load_traffic(dom_name, dom_bytes)
+    traffic = load_traffic(dom_name, dom_bytes, kmain / kx)
     total_bytes = plan.model_bytes(-1)
     kernels = [plan.kernel(k) for k in range(5)]
 
@@ -327,7 +362,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(256 if n >= 256 else n)
+        cpu = cpu_baseline(n)
 
     out = {
         "metric": "grid points/s (512^3 unbounded Poisson solve, FP32)",
@@ -355,9 +390,10 @@ def main():
                                "flops_per_launch": z_flops,
                                "peak_basis": "256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, FP32 without packed math"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "kernel": dom_name,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name,
+                     "launch_ms": round(float(per_pass[dom]), 4),
                      "algorithmic_bytes_per_launch": dom_bytes,
-                     "traffic": traffic},
+                     "columns_per_launch": "%d of %d" % (kmain, kx)},
         "cpu_baseline": cpu,
     }
     out.update(extra)

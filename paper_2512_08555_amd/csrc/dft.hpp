@@ -148,27 +148,68 @@ __device__ __forceinline__ void dft(cx<T>* v) {
   }
 }
 
-// DFT of length R (even) whose upper half v[R/2 .. R) is zero: one
-// decimation-in-frequency stage with a zero partner is a copy and a twiddle,
+// DFT of length R (even) whose upper half v[R/2 .. R) is zero.  Reads
+// v[0 .. R/2), writes all R outputs in natural order.
+//
+// When R = 4 m with m even, the decimation in time of dft() keeps the zeros
+// where they are: sub-DFT s takes x[4 n + s], which is zero exactly for
+// n >= m/2, so every sub-DFT is again half-zero (a length-4 one with two
+// zero inputs is four additions), followed by dft()'s radix-4 combine.
+// Otherwise one decimation-in-frequency stage with a zero partner is a copy
+// and a twiddle,
 //   X[2j]   = DFT_{R/2}(x[n])[j],  X[2j+1] = DFT_{R/2}(x[n] w_R^n)[j].
-// Reads v[0 .. R/2), writes all R outputs in natural order.
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_half_in(cx<T>* v) {
   static_assert(R % 2 == 0, "half-zero input needs an even length");
   constexpr int H = R / 2;
-  cx<T> a[H], b[H];
-  static_for<0, H>([&](auto nn) {
-    constexpr int n = decltype(nn)::value;
-    a[n] = v[n];
-    b[n] = twiddle_c<n, R, DIR>(v[n]);
-  });
-  dft<H, DIR>(a);
-  dft<H, DIR>(b);
-  static_for<0, H>([&](auto jj) {
-    constexpr int j = decltype(jj)::value;
-    v[2 * j] = a[j];
-    v[2 * j + 1] = b[j];
-  });
+  if constexpr (R == 2) {
+    v[1] = v[0];
+  } else if constexpr (R == 4) {
+    const cx<T> y0 = v[0], y1 = v[1];
+    const cx<T> e = mul_i<DIR>(y1);
+    v[0] = y0 + y1;
+    v[2] = y0 - y1;
+    v[1] = y0 + e;
+    v[3] = y0 - e;
+  } else if constexpr (R % 8 == 0) {
+    constexpr int m = R / 4;
+    cx<T> sub[4][m];
+    static_for<0, 4>([&](auto ss) {
+      constexpr int s = decltype(ss)::value;
+      static_for<0, m / 2>([&](auto nn) {
+        constexpr int n = decltype(nn)::value;
+        sub[s][n] = v[4 * n + s];
+      });
+      dft_half_in<m, DIR>(sub[s]);
+    });
+    static_for<0, m>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const cx<T> x0 = sub[0][k];
+      const cx<T> t1 = twiddle_c<(long long)k, R, DIR>(sub[1][k]);
+      cx<T> a, b, c, d;
+      pm_pair<(long long)2 * k, R, DIR>(x0, sub[2][k], a, b);
+      pm_pair<(long long)3 * k, R, DIR>(t1, sub[3][k], c, d);
+      const cx<T> e = mul_i<DIR>(d);
+      v[k] = a + c;
+      v[k + m] = b + e;
+      v[k + 2 * m] = a - c;
+      v[k + 3 * m] = b - e;
+    });
+  } else {
+    cx<T> a[H], b[H];
+    static_for<0, H>([&](auto nn) {
+      constexpr int n = decltype(nn)::value;
+      a[n] = v[n];
+      b[n] = twiddle_c<n, R, DIR>(v[n]);
+    });
+    dft<H, DIR>(a);
+    dft<H, DIR>(b);
+    static_for<0, H>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      v[2 * j] = a[j];
+      v[2 * j + 1] = b[j];
+    });
+  }
 }
 
 // DFT of length R (even) of which only outputs X[0 .. R/2) are needed:
