@@ -18,6 +18,10 @@ multiresolution grids"):
 * ``solve``    -- u = h^2 (G1 * f) on the box: the zero-padded FFT
                   convolution, the same product without pruning, and the
                   brute-force lattice sum that defines it.
+* ``bc``       -- the solve with a boundary condition per axis (unbounded,
+                  periodic, even, odd; Sec. 2.2 and eq. 2unbkernel), by one
+                  plain transform per axis, and the lower-dimensional lattice
+                  Green's functions it needs.
 * ``analytic`` -- closed forms used as pins: Watson's constant, the Gaussian
                   charge potential, the paper's compact manufactured solution
                   (Sec. 4.2, unbounded domains).
@@ -30,12 +34,12 @@ from .lgf import (watson_g0, lgf_table, lgf_point_adaptive, lgf_far_field,
 from .spectrum import green_spectrum_raw, green_spectrum_rfft, green_spectrum_scaled
 from .solve import (solve, solve_full, brute_force, brute_force_adjoint,
                     adjoint, laplacian7_interior)
-from . import analytic
+from . import analytic, bc
 
 __all__ = [
     "watson_g0", "lgf_table", "lgf_point_adaptive", "lgf_far_field", "lgf_tail",
     "quadrature_nodes", "hankel_coefficients",
     "green_spectrum_raw", "green_spectrum_rfft", "green_spectrum_scaled",
     "solve", "solve_full", "brute_force", "brute_force_adjoint", "adjoint",
-    "laplacian7_interior", "analytic",
+    "laplacian7_interior", "analytic", "bc",
 ]
