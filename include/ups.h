@@ -18,6 +18,15 @@
  * axis (default 2 N_i), with the real, even spectrum G_hat of the evenly
  * periodised G1 computed once by ups_plan_setup.
  *
+ * A direction may instead be periodic (ups_bc): the kernel is then the
+ * Green's function that is periodic along it, the spectral expression of
+ * the LGF there (Sec. 2.2).  With two unbounded directions the kernel is
+ * eq. 2unbkernel's: the two-dimensional LGF's spectrum on the zero
+ * wavenumber of the periodic direction, the inverse symbol elsewhere; with
+ * one, the LGF of the one-dimensional operator screened by the periodic
+ * directions' symbol (closed-form); with none, the inverse symbol, zero at
+ * wavenumber 0 (the mean-free solution of the mean-free source).
+ *
  * Conventions for every call:
  *   - Every call returns a ups_status; on failure ups_last_error() holds a
  *     message (thread-local, valid until the next call on that thread).
@@ -63,8 +72,9 @@ typedef enum {
 } ups_status;
 
 /* Boundary condition per axis side (Sec. 2.2: unbounded, periodic, even =
- * homogeneous Neumann, odd = homogeneous Dirichlet).  The library solves
- * UPS_BC_UNB on all six sides; anything else is UPS_ERR_UNSUPPORTED. */
+ * homogeneous Neumann, odd = homogeneous Dirichlet).  Both sides of an axis
+ * carry the same condition.  The library solves UPS_BC_UNB and UPS_BC_PER
+ * in any combination; UPS_BC_EVEN and UPS_BC_ODD are UPS_ERR_UNSUPPORTED. */
 typedef enum { UPS_BC_UNB = 0, UPS_BC_PER = 1, UPS_BC_EVEN = 2, UPS_BC_ODD = 3 } ups_bc;
 
 /* Green's kernel: the LGF of the operator the caller discretises with
@@ -84,14 +94,16 @@ typedef enum { UPS_CELL = 0, UPS_NODE = 1 } ups_center;
 typedef struct {
   int n[3];        /* grid points per axis, (x, y, z); each >= 2          */
   double h[3];     /* grid spacing per axis; must be equal (isotropic)    */
-  int bc[3][2];    /* ups_bc per axis (x, y, z) and side (low, high)      */
+  int bc[3][2];    /* ups_bc per axis (x, y, z) and side (low, high); the
+                      two sides of an axis must be equal                  */
   int green;       /* ups_green                                           */
   int prec;        /* ups_prec                                            */
   int center;      /* ups_center                                          */
   int ncomp;       /* components solved together (1..8), e.g. 3 for a
                       vector right-hand side; they share G_hat            */
   int pad[3];      /* padded FFT length per axis; 0 = 2 n. Must be even,
-                      >= 2 n and a supported length (ups_supported_length) */
+                      >= 2 n and a supported length (ups_supported_length);
+                      exactly 2 n along a periodic axis                   */
 } ups_problem;
 
 typedef struct ups_plan_s* ups_plan_t;
@@ -113,8 +125,10 @@ void ups_problem_init(ups_problem* p);
 
 /* Validate the problem and build a host-side plan (no device work).
  * Errors: INVALID_ARG (null, n < 2, h <= 0, ncomp out of range, pad below
- * 2 n or odd), UNSUPPORTED (non-UNB side, Mehrstellen kernel, anisotropic h,
- * n > 4096, padded length without a compiled kernel). */
+ * 2 n or odd, pad other than 2 n along a periodic axis), UNSUPPORTED (the
+ * two sides of an axis differ, an even or odd direction, Mehrstellen
+ * kernel, anisotropic h, n > 4096, padded length without a compiled
+ * kernel, per-lane offsets that would not fit 32 bits). */
 ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out);
 
 /* Bytes the caller must provide: green = G_hat octant plus twiddle tables,
@@ -125,7 +139,13 @@ ups_status ups_plan_sizes(ups_plan_t plan, size_t* green_bytes, size_t* work_byt
 /* Bind the caller's buffers to the plan and build G_hat (Sec. 2.2) into
  * `green`: G1 on the octant [0, M_i/2] by a separable Bessel quadrature in
  * double, its DCT-I along the three axes, times h^2 / (Mx My Mz), rounded to
- * the plan's precision.  Enqueued on `stream`, then the host waits for it.
+ * the plan's precision.  With periodic directions: the two-dimensional LGF
+ * by the same quadrature or the screened one-dimensional LGF in closed form
+ * (DCT-I along the unbounded axes), the inverse symbol elsewhere, and along
+ * each periodic axis (padded to M = 2 n) twice the n-point spectrum at even
+ * frequencies and zero at odd ones -- the spectrum of the n-periodic kernel
+ * truncated to |d| < n, which the zero-padded convolution applies exactly.
+ * Enqueued on `stream`, then the host waits for it.
  * The buffers must stay alive and unchanged (green) for every later solve.
  * Errors: INVALID_ARG (null or misaligned pointers), WORKSPACE (sizes smaller
  * than ups_plan_sizes), DEVICE (no gfx950 device or a HIP error). */

@@ -67,10 +67,13 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
     for (int s = 0; s < 2; ++s) {
       if (p->bc[i][s] < UPS_BC_UNB || p->bc[i][s] > UPS_BC_ODD)
         return fail(UPS_ERR_INVALID_ARG, "bc[%d][%d] = %d is not a ups_bc", i, s, p->bc[i][s]);
-      if (p->bc[i][s] != UPS_BC_UNB)
-        return fail(UPS_ERR_UNSUPPORTED, "bc[%d][%d]: only unbounded sides are solved", i, s);
     }
+    if (p->bc[i][0] != p->bc[i][1])
+      return fail(UPS_ERR_UNSUPPORTED, "bc[%d]: both sides of an axis must carry the same condition", i);
+    if (p->bc[i][0] == UPS_BC_EVEN || p->bc[i][0] == UPS_BC_ODD)
+      return fail(UPS_ERR_UNSUPPORTED, "bc[%d]: even and odd directions are not solved", i);
   }
+  const bool any_spectral = p->bc[0][0] != UPS_BC_UNB || p->bc[1][0] != UPS_BC_UNB || p->bc[2][0] != UPS_BC_UNB;
   if (std::fabs(p->h[0] - p->h[1]) > 1e-12 * p->h[0] || std::fabs(p->h[0] - p->h[2]) > 1e-12 * p->h[0])
     return fail(UPS_ERR_UNSUPPORTED, "anisotropic spacing is not supported (h must be equal)");
   if (p->green < UPS_GREEN_LGF2 || p->green > UPS_GREEN_LGF6_MEHR)
@@ -90,7 +93,15 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
     M[i] = p->pad[i] ? p->pad[i] : 2 * p->n[i];
     if (M[i] % 2 || M[i] < 2 * p->n[i])
       return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: must be even and >= 2 n = %d", i, M[i], 2 * p->n[i]);
+    // a periodic direction is padded to exactly 2 n: its kernel is the
+    // n-periodic Green's function, whose spectrum lives on the even
+    // frequencies of that grid
+    if (p->bc[i][0] == UPS_BC_PER && M[i] != 2 * p->n[i])
+      return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: a periodic direction takes pad = 2 n = %d (or 0)", i, M[i],
+                  2 * p->n[i]);
   }
+  if (any_spectral && p->green != UPS_GREEN_LGF2)
+    return fail(UPS_ERR_UNSUPPORTED, "non-unbounded directions are solved with the 7-point kernel only");
   for (int i = 0; i < 3; ++i) {
     if (!length_supported(M[i], f64))
       return fail(UPS_ERR_UNSUPPORTED, "padded length %d (axis %d) has no compiled %s kernel", M[i], i,
@@ -111,6 +122,7 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   g->gz = int(align_up(size_t(g->oz), 16));
   g->ncomp = p->ncomp;
   g->h = p->h[0];
+  for (int i = 0; i < 3; ++i) g->bc[i] = p->bc[i][0];
   // Every kernel addresses W as a wave-uniform 64-bit base plus a 32-bit
   // per-lane byte offset of at most 64 line strides (a row of a 64-row
   // block or of a split factor <= 64) plus a tile column; the longest line
@@ -480,7 +492,7 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   if (e == hipSuccess) e = build_twiddles(g.f64, g.my, gb + g.off_twy, work, st);
   if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, gb + g.off_twz, work, st);
   if (e == hipSuccess)
-    e = build_green(g.f64, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
+    e = build_green(g.f64, g.bc, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
   if (e == hipSuccess) e = enqueue_set_word(reinterpret_cast<unsigned*>(gb + g.off_status), 0u, st);
   if (e == hipSuccess && g.guard) {
     // canary bands below and above W (the Green's build used them as scratch)

@@ -26,6 +26,7 @@
 
 #include "green.hpp"
 #include "cplx.hpp"
+#include "../../include/ups.h"
 
 namespace ups {
 
@@ -358,6 +359,195 @@ hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int m
   return hipStreamSynchronize(st);
 }
 
+// ---------------------------------------------------------------------------
+// Directions that are not all unbounded (Sec. 2.2).  Axis indices 0, 1, 2 =
+// x, y, z; octant index m_i in [0, M_i/2] of the padded grid; the symbol of
+// the 3-point second difference at m_i is s_i = 4 sin^2(pi m_i / M_i).
+//   * No unbounded direction: G~ = -1/sigma, sigma = sum s_i (0 at sigma = 0).
+//   * One unbounded direction a: for each transverse mode (m_b, m_c) the
+//     decaying solution of G[n+1] - 2 G[n] + G[n-1] - s G[n] = delta[n],
+//     s = s_b + s_c, is G[n] = -rho^|n| / sqrt(s (s+4)) with
+//     rho = 1 / (1 + s/2 + sqrt(s + s^2/4)) (the one-dimensional LGF |n|/2
+//     at s = 0); its DCT-I along a.
+//   * Two unbounded directions a, b (eq. 2unbkernel): at m_c = 0 the DCT-I of
+//     the two-dimensional LGF, normalised by G[0, 0] = 0,
+//       G[n] = -\int_0^inf (e^{-4t} I_{n_a}(2t) I_{n_b}(2t) - e^{-4t} I_0(2t)^2) dt,
+//     by the quadrature and Hankel tail of the three-dimensional one (the
+//     leading tail terms cancel); -1/sigma at every other m_c.
+// A periodic direction of N points is zero-padded to M = 2N like an
+// unbounded one: the kernel then is the N-periodic Green's function on
+// |d| < N, whose DFT on the 2N grid is twice its N-point spectrum at even
+// m and zero at odd m.  The stored value is h^2 / (Mx My Mz) times
+// G~ times that weight.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double symbol_1d(int m, int M) {
+  const double sv = sin(kPi * double(m) / double(M));
+  return 4.0 * sv * sv;
+}
+
+__global__ void k_lgf2d(const double* __restrict__ B, const double* __restrict__ w, int J, int k0, int k1,
+                        double T, double* __restrict__ out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)k0 * k1) return;
+  const int n0 = int(idx / k1), n1 = int(idx % k1);
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double b0 = B[(size_t)j];
+    acc = fma(w[j], B[(size_t)n0 * J + j] * B[(size_t)n1 * J + j] - b0 * b0, acc);
+  }
+  // tail: sum over a + b = m >= 1 of (c_a(n0) c_b(n1) - c_a(0) c_b(0))
+  // \int_T^inf (4 pi t)^-1 (2t)^-m dt
+  double tail = 0.0;
+  for (int a = 0; a <= kTailK; ++a)
+    for (int b = 0; a + b <= kTailK; ++b) {
+      const int m = a + b;
+      if (m == 0) continue;
+      const double g = pow(2.0, -m) * pow(T, -double(m)) / (4.0 * kPi * m);
+      tail += g * (hankel_c(a, n0) * hankel_c(b, n1) - hankel_c(a, 0) * hankel_c(b, 0));
+    }
+  out[idx] = -(acc + tail);
+}
+
+// Tt[t][n] = screened 1-D LGF at offset n < ka for transverse mode
+// t = mb kc + mc (mb < kb, mc < kc)
+__global__ void k_lgf1d_table(int ka, int kb, int kc, int Mb, int Mc, double* __restrict__ out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)ka * kb * kc) return;
+  const int n = int(idx % ka);
+  const long long t = idx / ka;
+  const int mb = int(t / kc), mc = int(t % kc);
+  const double s = symbol_1d(mb, Mb) + symbol_1d(mc, Mc);
+  double v;
+  if (s == 0.0) {
+    v = 0.5 * n;
+  } else {
+    const double root = sqrt(s * (s + 4.0));
+    const double log_rho = -log1p(0.5 * s + 0.5 * root);
+    v = -exp(double(n) * log_rho) / root;
+  }
+  out[idx] = v;
+}
+
+struct MixedBc {
+  int bc[3];       // ups_bc per axis (x, y, z)
+  int M[3];        // padded lengths
+  int K[3];        // octant extents M/2 + 1
+  int du;          // unbounded directions
+  int a, b, c;     // du = 1: a unbounded, b < c the others; du = 2: a < b unbounded, c the other
+};
+
+template <typename T>
+__global__ void k_store_ghat_mixed(MixedBc q, const double* __restrict__ D, int gz, double scale,
+                                   T* __restrict__ g) {
+  const long long tot = (long long)q.K[0] * q.K[1] * q.K[2];
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  int m[3];
+  m[0] = int(idx % q.K[0]);
+  m[1] = int((idx / q.K[0]) % q.K[1]);
+  m[2] = int(idx / ((long long)q.K[0] * q.K[1]));
+  double wgt = 1.0;
+  for (int i = 0; i < 3; ++i)
+    if (q.bc[i] == UPS_BC_PER) wgt *= (m[i] & 1) ? 0.0 : 2.0;
+  double v = 0.0;
+  if (wgt != 0.0) {
+    const double sigma = symbol_1d(m[0], q.M[0]) + symbol_1d(m[1], q.M[1]) + symbol_1d(m[2], q.M[2]);
+    if (q.du == 0) {
+      v = sigma > 0.0 ? -1.0 / sigma : 0.0;
+    } else if (q.du == 1) {
+      const long long t = (long long)m[q.b] * q.K[q.c] + m[q.c];
+      v = D[(long long)m[q.a] * ((long long)q.K[q.b] * q.K[q.c]) + t];
+    } else {
+      v = m[q.c] == 0 ? D[(long long)m[q.a] * q.K[q.b] + m[q.b]] : -1.0 / sigma;
+    }
+  }
+  g[((long long)m[1] * q.K[0] + m[0]) * gz + m[2]] = T(scale * wgt * v);  // [iy][kx][iz]
+}
+
+template <typename T>
+hipError_t build_green_mixed_t(const int bc[3], int kz, int ky, int kx, int gz, double h, int mx, int my,
+                               int mz, void* ghat, void* scratch, hipStream_t st) {
+  const GreenScratch L = green_scratch_layout(kz, ky, kx);
+  char* base = static_cast<char*>(scratch);
+  auto P = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  MixedBc q{};
+  const int Ms[3] = {mx, my, mz}, Ks[3] = {kx, ky, kz};
+  int unb[3], spec[3], nu = 0, ns = 0;
+  for (int i = 0; i < 3; ++i) {
+    q.bc[i] = bc[i];
+    q.M[i] = Ms[i];
+    q.K[i] = Ks[i];
+    if (bc[i] == UPS_BC_UNB) unb[nu++] = i;
+    else spec[ns++] = i;
+  }
+  q.du = nu;
+  const size_t cofs[3] = {L.off_Cx, L.off_Cy, L.off_Cz};
+  std::vector<double> Ca, Cb, t, w;  // host data of the asynchronous copies
+  const double* D = nullptr;
+  if (nu == 1) {
+    q.a = unb[0];
+    q.b = spec[0];
+    q.c = spec[1];
+    const int ka = Ks[q.a], kb = Ks[q.b], kc = Ks[q.c];
+    const long long ntr = (long long)kb * kc;
+    const long long n = ntr * ka;
+    hipLaunchKernelGGL(k_lgf1d_table, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, ka, kb, kc, Ms[q.b],
+                       Ms[q.c], P(L.off_G0));
+    GCHECK(hipGetLastError());
+    cosine_matrix(ka, Ca);
+    GCHECK(hipMemcpyAsync(P(cofs[q.a]), Ca.data(), sizeof(double) * Ca.size(), hipMemcpyHostToDevice, st));
+    // DCT-I along a: out[ma][t] = sum_n C[ma][n] Tt[t][n]
+    dim3 grid(unsigned((ntr + GT - 1) / GT), (ka + GT - 1) / GT, 1);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(cofs[q.a]), ka, P(L.off_G0), int(ntr), ka,
+                       (const double*)nullptr, 0LL, 1.0, P(L.off_G1), 0LL);
+    GCHECK(hipGetLastError());
+    D = P(L.off_G1);
+  } else if (nu == 2) {
+    q.a = unb[0];
+    q.b = unb[1];
+    q.c = spec[0];
+    const int ka = Ks[q.a], kb = Ks[q.b];
+    const int kmax = std::max(ka, kb);
+    double Tsplit;
+    lgf_quadrature(kmax - 1, t, w, &Tsplit);
+    const int J = int(t.size());
+    GCHECK(hipMemcpyAsync(P(L.off_t), t.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
+    GCHECK(hipMemcpyAsync(P(L.off_w), w.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_bessel_ive, dim3((J + 63) / 64), dim3(64), 0, st, P(L.off_t), J, kmax, P(L.off_B));
+    GCHECK(hipGetLastError());
+    const long long n = (long long)ka * kb;
+    hipLaunchKernelGGL(k_lgf2d, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P(L.off_B), P(L.off_w), J,
+                       ka, kb, Tsplit, P(L.off_G0));
+    GCHECK(hipGetLastError());
+    cosine_matrix(ka, Ca);
+    cosine_matrix(kb, Cb);
+    GCHECK(hipMemcpyAsync(P(cofs[q.a]), Ca.data(), sizeof(double) * Ca.size(), hipMemcpyHostToDevice, st));
+    GCHECK(hipMemcpyAsync(P(cofs[q.b]), Cb.data(), sizeof(double) * Cb.size(), hipMemcpyHostToDevice, st));
+    // along b: out[mb][na] = sum_nb Cb[mb][nb] G2[na][nb]
+    {
+      dim3 grid((ka + GT - 1) / GT, (kb + GT - 1) / GT, 1);
+      hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(cofs[q.b]), kb, P(L.off_G0), ka, kb,
+                         (const double*)nullptr, 0LL, 1.0, P(L.off_G1), 0LL);
+      GCHECK(hipGetLastError());
+    }
+    // along a: out[ma][mb] = sum_na Ca[ma][na] out1[mb][na]
+    {
+      dim3 grid((kb + GT - 1) / GT, (ka + GT - 1) / GT, 1);
+      hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(cofs[q.a]), ka, P(L.off_G1), kb, ka,
+                         (const double*)nullptr, 0LL, 1.0, P(L.off_G0), 0LL);
+      GCHECK(hipGetLastError());
+    }
+    D = P(L.off_G0);
+  }
+  const double scale = (h * h) / (double(mx) * double(my) * double(mz));
+  const long long tot = (long long)kz * ky * kx;
+  hipLaunchKernelGGL((k_store_ghat_mixed<T>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, q, D, gz,
+                     scale, static_cast<T*>(ghat));
+  GCHECK(hipGetLastError());
+  // the host vectors above must outlive the copies
+  return hipStreamSynchronize(st);
+}
+
 template <typename T>
 __global__ void k_twiddles(const double* __restrict__ src, int n, cx<T>* __restrict__ dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -408,10 +598,16 @@ hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t build_green(bool f64, int kz, int ky, int kx, int gz, double h, int mx, int my, int mz, void* ghat,
-                       void* scratch, hipStream_t st) {
-  hipError_t e = f64 ? build_green_t<double>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
-                     : build_green_t<float>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
+hipError_t build_green(bool f64, const int bc[3], int kz, int ky, int kx, int gz, double h, int mx, int my,
+                       int mz, void* ghat, void* scratch, hipStream_t st) {
+  const bool all_unb = !bc || (bc[0] == UPS_BC_UNB && bc[1] == UPS_BC_UNB && bc[2] == UPS_BC_UNB);
+  hipError_t e;
+  if (all_unb)
+    e = f64 ? build_green_t<double>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
+            : build_green_t<float>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
+  else
+    e = f64 ? build_green_mixed_t<double>(bc, kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
+            : build_green_mixed_t<float>(bc, kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
 }

@@ -22,9 +22,12 @@ GreenScratch green_scratch_layout(int kz, int ky, int kx);
 void lgf_quadrature(int n_max, std::vector<double>& t, std::vector<double>& w, double* T_out);
 
 // Ghat[iy][kx][iz] (iz pitch gz) = h^2/(mx my mz) * DCT-I(G1) on the octant
-// kz x ky x kx = (mz/2+1) x (my/2+1) x (mx/2+1); waits for completion.
-hipError_t build_green(bool f64, int kz, int ky, int kx, int gz, double h, int mx, int my, int mz,
-                       void* ghat, void* scratch, hipStream_t st);
+// kz x ky x kx = (mz/2+1) x (my/2+1) x (mx/2+1) when every direction is
+// unbounded (bc NULL or all UPS_BC_UNB); otherwise the mixed kernel of
+// build_green_mixed_t (green.hip) for the ups_bc per axis bc[0..2] = x, y, z.
+// Waits for completion.
+hipError_t build_green(bool f64, const int bc[3], int kz, int ky, int kx, int gz, double h, int mx, int my,
+                       int mz, void* ghat, void* scratch, hipStream_t st);
 
 // dst[m] = exp(-2 pi i m / M), m < M, complex float or double; waits.
 // Complex entries of one axis's twiddle table: M (exp(-2 pi i m / M)), a

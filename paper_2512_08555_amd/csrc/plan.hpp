@@ -16,6 +16,7 @@ struct PlanGeom {
   int px;                    // row pitch of W (elements)
   int gz;                    // iz pitch of G_hat [iy][kx][iz] (elements)
   int ncomp;
+  int bc[3];                 // ups_bc per axis (x, y, z); both sides equal
   double h;
   long long plane, comp_w;   // W strides (complex elements)
   size_t solve_work;         // bytes of W

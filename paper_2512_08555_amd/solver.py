@@ -19,8 +19,13 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def make_problem(shape, h, prec="f64", ncomp=1, pad=None):
-    """ups_problem for a grid of shape (nz, ny, nx) with isotropic spacing h."""
+BC_CODES = {"unb": capi.UPS_BC_UNB, "per": capi.UPS_BC_PER, "even": capi.UPS_BC_EVEN, "odd": capi.UPS_BC_ODD}
+
+
+def make_problem(shape, h, prec="f64", ncomp=1, pad=None, bc=None):
+    """ups_problem for a grid of shape (nz, ny, nx) with isotropic spacing h;
+    bc: None (unbounded everywhere) or one of "unb", "per", "even", "odd"
+    per axis in (z, y, x) order, the same on both sides of the axis."""
     nz, ny, nx = (int(v) for v in shape)
     p = capi.ups_problem()
     capi.lib().ups_problem_init(C.byref(p))
@@ -32,6 +37,10 @@ def make_problem(shape, h, prec="f64", ncomp=1, pad=None):
     if pad is not None:
         mz, my, mx = (int(v) for v in pad)
         p.pad[0], p.pad[1], p.pad[2] = mx, my, mz
+    if bc is not None:
+        codes = [BC_CODES[b] if isinstance(b, str) else int(b) for b in bc]
+        for axis, code in zip((2, 1, 0), codes):   # (z, y, x) -> ABI axis index
+            p.bc[axis][0] = p.bc[axis][1] = code
     return p
 
 
@@ -42,14 +51,15 @@ class Plan:
     by the constructor unless setup=False) allocates the green and work
     buffers with torch on the current device and builds G_hat."""
 
-    def __init__(self, shape, h, prec="f64", ncomp=1, pad=None, setup=True, problem=None):
+    def __init__(self, shape, h, prec="f64", ncomp=1, pad=None, setup=True, problem=None, bc=None):
         self.shape = tuple(int(v) for v in shape)
         self.h = float(h)
         self.prec = prec
         self.ncomp = int(ncomp)
+        self.bc = tuple(bc) if bc is not None else ("unb",) * 3
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         L = capi.lib()
-        self._prob = problem if problem is not None else make_problem(self.shape, h, prec, ncomp, pad)
+        self._prob = problem if problem is not None else make_problem(self.shape, h, prec, ncomp, pad, bc)
         handle = C.c_void_p()
         capi.check(L.ups_plan_create(C.byref(self._prob), C.byref(handle)))
         self._h = handle
@@ -257,7 +267,7 @@ class Batch:
     """Many independent solves (uneven shapes, vector right-hand sides) run
     as one hipGraph launch (ups_batch_*).
 
-    specs: list of dicts {shape: (nz, ny, nx), h, prec, ncomp, pad}."""
+    specs: list of dicts {shape: (nz, ny, nx), h, prec, ncomp, pad, bc}."""
 
     def __init__(self, specs, setup=True):
         from .lengths import auto_pad
@@ -268,9 +278,11 @@ class Batch:
             shape = tuple(int(v) for v in sp["shape"])
             prec = sp.get("prec", "f32")
             ncomp = int(sp.get("ncomp", 1))
+            bc = sp.get("bc")
             pad = sp.get("pad") or auto_pad(shape, prec)
-            probs[i] = make_problem(shape, sp["h"], prec, ncomp, pad)
-            self.specs.append(dict(shape=shape, h=float(sp["h"]), prec=prec, ncomp=ncomp, pad=tuple(pad)))
+            probs[i] = make_problem(shape, sp["h"], prec, ncomp, pad, bc)
+            self.specs.append(dict(shape=shape, h=float(sp["h"]), prec=prec, ncomp=ncomp, pad=tuple(pad),
+                                   bc=tuple(bc) if bc is not None else ("unb",) * 3))
         handle = C.c_void_p()
         capi.check(L.ups_batch_create(probs, len(specs), C.byref(handle)))
         self._h = handle

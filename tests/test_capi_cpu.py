@@ -69,10 +69,30 @@ def test_validation_errors():
     p.h[2] = -1.0
     assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG
 
+    # boundary conditions: the same on both sides of an axis; periodic
+    # directions padded to exactly 2 n; even and odd directions not solved
     p = make_problem((32, 32, 32), 1 / 32)
     p.bc[1][0] = capi.UPS_BC_PER
     s, _, msg = _create(p)
-    assert s == capi.UPS_ERR_UNSUPPORTED and "unbounded" in msg
+    assert s == capi.UPS_ERR_UNSUPPORTED and "both sides" in msg
+    p = make_problem((32, 32, 32), 1 / 32, bc=("per", "unb", "unb"))
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    L.ups_plan_destroy(h)
+    p = make_problem((32, 32, 32), 1 / 32, bc=("per", "per", "per"))
+    s, h, _ = _create(p)
+    assert s == capi.UPS_OK
+    L.ups_plan_destroy(h)
+    p = make_problem((30, 32, 32), 1 / 32, pad=(64, 64, 64), bc=("per", "unb", "unb"))
+    s, _, msg = _create(p)
+    assert s == capi.UPS_ERR_INVALID_ARG and "periodic" in msg
+    for b in ("even", "odd"):
+        p = make_problem((32, 32, 32), 1 / 32, bc=("unb", b, "unb"))
+        s, _, msg = _create(p)
+        assert s == capi.UPS_ERR_UNSUPPORTED and "even and odd" in msg
+    p = make_problem((32, 32, 32), 1 / 32, bc=("per", "unb", "unb"))
+    p.green = capi.UPS_GREEN_LGF4_MEHR
+    assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
 
     p = make_problem((32, 32, 32), 1 / 32)
     p.green = capi.UPS_GREEN_LGF4_MEHR

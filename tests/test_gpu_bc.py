@@ -1,0 +1,106 @@
+"""Periodic directions mixed with unbounded ones (Sec. 2.2, eq. 2unbkernel)
+through the C ABI, against the oracle's plain per-axis solve."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bc as obc
+from paper_2512_08555_amd import workloads
+from paper_2512_08555_amd.lengths import auto_pad
+from paper_2512_08555_amd.solver import Batch, Plan
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-6}
+PER_UNB = [b for b in itertools.product(("unb", "per"), repeat=3) if "per" in b]
+
+
+def _rel_inf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _pads(shape, bc, prec):
+    """2 n along periodic axes, the smallest supported length >= 2 n along
+    unbounded ones."""
+    ap = auto_pad(shape, prec)
+    return tuple(2 * n if b == "per" else m for n, b, m in zip(shape, bc, ap))
+
+
+def _source(shape, h, seed):
+    return workloads.blob_source(shape, h, seed=seed, nblobs=5, sigma=(0.05, 0.12), noise=1e-3)
+
+
+def _run(shape, bc, prec, seed, ncomp=1):
+    h = 1.0 / max(shape)
+    pad = _pads(shape, bc, prec)
+    print("[case] bc %s %s shape %s pad %s ncomp %d" % (bc, prec, shape, pad, ncomp), flush=True)
+    if ncomp == 1:
+        f = _source(shape, h, seed)
+    else:
+        f = np.stack([_source(shape, h, seed + c) for c in range(ncomp)])
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    plan = Plan(shape, h, prec, ncomp=ncomp, pad=pad, bc=bc)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    comps = [(u, f)] if ncomp == 1 else [(u[c], f[c]) for c in range(ncomp)]
+    worst = 0.0
+    for uc, fc in comps:
+        ref = obc.solve_bc(fc, h, bc, M=pad)
+        worst = max(worst, _rel_inf(uc, ref))
+    print("  rel Linf %.3e" % worst, flush=True)
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bc", PER_UNB)
+def test_periodic_mixes_match_oracle(bc, prec):
+    # periodic axes of 16 or 32 points (2 n a compiled length), unbounded
+    # axes of uneven sizes padded to the next compiled length
+    shape = tuple(32 if b == "per" and i == 0 else 16 if b == "per" else n
+                  for i, (b, n) in enumerate(zip(bc, (20, 27, 13))))
+    assert _run(shape, bc, prec, seed=len(shape) + hash(bc) % 97) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_two_unbounded_one_periodic_vector_source(prec):
+    assert _run((32, 30, 21), ("per", "unb", "unb"), prec, seed=3, ncomp=3) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_two_unbounded_one_periodic_128(prec):
+    # the configuration of the paper's vortex tube: periodic along z,
+    # unbounded in x and y, one wave per line in every pass (pads 256)
+    assert _run((128, 128, 128), ("per", "unb", "unb"), prec, seed=21) < TOL[prec]
+
+
+def test_fully_periodic_mean_free():
+    shape, bc = (32, 16, 64), ("per", "per", "per")
+    h = 1.0 / 64
+    f = _source(shape, h, 5)
+    f -= f.mean()
+    plan = Plan(shape, h, "f64", bc=bc)
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    ref = obc.solve_bc(f, h, bc)
+    assert abs(u.mean()) < 1e-14 * np.abs(u).max()
+    assert _rel_inf(u, ref) < 1e-12
+
+
+def test_batch_with_periodic_directions_equals_single_plans():
+    specs = [dict(shape=(32, 20, 27), h=1 / 32, prec="f32", bc=("per", "unb", "unb"), pad=(64, 64, 64)),
+             dict(shape=(16, 32, 32), h=1 / 32, prec="f32", bc=("unb", "per", "per"), pad=(32, 64, 64)),
+             dict(shape=(20, 20, 20), h=1 / 20, prec="f32", pad=(64, 64, 64)),
+             dict(shape=(16, 16, 16), h=1 / 16, prec="f32", bc=("per",) * 3, pad=(32, 32, 32))]
+    print("[case] batch of %d problems with periodic directions" % len(specs), flush=True)
+    b = Batch(specs)
+    fs = [torch.from_numpy(_source(sp["shape"], sp["h"], 40 + i).astype(np.float32)).cuda()
+          for i, sp in enumerate(specs)]
+    us = b.solve(fs)
+    torch.cuda.synchronize()
+    for i, sp in enumerate(b.specs):
+        p = Plan(sp["shape"], sp["h"], "f32", pad=sp["pad"], bc=sp["bc"])
+        assert torch.equal(p.solve(fs[i]), us[i]), i
+        ref = obc.solve_bc(fs[i].double().cpu().numpy(), sp["h"], sp["bc"], M=sp["pad"])
+        assert _rel_inf(us[i].double().cpu().numpy(), ref) < TOL["f32"], i
