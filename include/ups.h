@@ -18,9 +18,11 @@
  * axis (default 2 N_i), with the real, even spectrum G_hat of the evenly
  * periodised G1 computed once by ups_plan_setup.
  *
- * A direction may instead be periodic (ups_bc): the kernel is then the
- * Green's function that is periodic along it, the spectral expression of
- * the LGF there (Sec. 2.2).  With two unbounded directions the kernel is
+ * A direction may instead be periodic, even or odd (ups_bc): the kernel is
+ * then the Green's function that is periodic along it, the spectral
+ * expression of the LGF there (Sec. 2.2), applied to the source as it is
+ * (periodic) or to its even or odd mirror image about the box faces (the
+ * cosine and sine transforms of Sec. 2.2 as a length-2n DFT).  With two unbounded directions the kernel is
  * eq. 2unbkernel's: the two-dimensional LGF's spectrum on the zero
  * wavenumber of the periodic direction, the inverse symbol elsewhere; with
  * one, the LGF of the one-dimensional operator screened by the periodic
@@ -73,8 +75,12 @@ typedef enum {
 
 /* Boundary condition per axis side (Sec. 2.2: unbounded, periodic, even =
  * homogeneous Neumann, odd = homogeneous Dirichlet).  Both sides of an axis
- * carry the same condition.  The library solves UPS_BC_UNB and UPS_BC_PER
- * in any combination; UPS_BC_EVEN and UPS_BC_ODD are UPS_ERR_UNSUPPORTED. */
+ * carry the same condition; every combination over the three axes is
+ * solved.  Even and odd directions are cell-centred (UPS_CELL): the ghost
+ * cell beyond a face is the mirror image (u[-1] = u[0], u[n] = u[n-1]) or
+ * its negative.  Periodic, even and odd directions take pad = 2 n; an even
+ * or odd direction needs a mirrored-fill kernel for that length (powers of
+ * two 32 .. 1024), and along x an even n. */
 typedef enum { UPS_BC_UNB = 0, UPS_BC_PER = 1, UPS_BC_EVEN = 2, UPS_BC_ODD = 3 } ups_bc;
 
 /* Green's kernel: the LGF of the operator the caller discretises with
@@ -103,7 +109,7 @@ typedef struct {
                       vector right-hand side; they share G_hat            */
   int pad[3];      /* padded FFT length per axis; 0 = 2 n. Must be even,
                       >= 2 n and a supported length (ups_supported_length);
-                      exactly 2 n along a periodic axis                   */
+                      exactly 2 n along a periodic, even or odd axis      */
 } ups_problem;
 
 typedef struct ups_plan_s* ups_plan_t;
@@ -125,10 +131,11 @@ void ups_problem_init(ups_problem* p);
 
 /* Validate the problem and build a host-side plan (no device work).
  * Errors: INVALID_ARG (null, n < 2, h <= 0, ncomp out of range, pad below
- * 2 n or odd, pad other than 2 n along a periodic axis), UNSUPPORTED (the
- * two sides of an axis differ, an even or odd direction, Mehrstellen
- * kernel, anisotropic h, n > 4096, padded length without a compiled
- * kernel, per-lane offsets that would not fit 32 bits). */
+ * 2 n or odd, pad other than 2 n along a periodic, even or odd axis),
+ * UNSUPPORTED (the two sides of an axis differ, an even or odd direction
+ * node-centred, of odd extent along x or without a mirrored-fill kernel,
+ * Mehrstellen kernel, anisotropic h, n > 4096, padded length without a
+ * compiled kernel, per-lane offsets that would not fit 32 bits). */
 ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out);
 
 /* Bytes the caller must provide: green = G_hat octant plus twiddle tables,
@@ -144,7 +151,9 @@ ups_status ups_plan_sizes(ups_plan_t plan, size_t* green_bytes, size_t* work_byt
  * (DCT-I along the unbounded axes), the inverse symbol elsewhere, and along
  * each periodic axis (padded to M = 2 n) twice the n-point spectrum at even
  * frequencies and zero at odd ones -- the spectrum of the n-periodic kernel
- * truncated to |d| < n, which the zero-padded convolution applies exactly.
+ * truncated to |d| < n, which the zero-padded convolution applies exactly;
+ * along an even or odd axis the 2n-periodic spectrum itself (the forward
+ * pass fills the second half of the line with the mirror image).
  * Enqueued on `stream`, then the host waits for it.
  * The buffers must stay alive and unchanged (green) for every later solve.
  * Errors: INVALID_ARG (null or misaligned pointers), WORKSPACE (sizes smaller
@@ -222,7 +231,10 @@ const char* ups_plan_kernel(ups_plan_t plan, int pass);
  * `len` in precision `prec` (ups_prec): writes up to `cap` of them to
  * `names` (static strings owned by the library; `names` may be NULL when cap
  * is 0) and returns how many exist (0 for bad arguments).  The first one is
- * the default a new plan uses when no tuning result is cached. */
+ * the default a new plan uses when no tuning result is cached.  Listed are
+ * the variants for unbounded and periodic directions; a forward pass along
+ * an even or odd direction runs the mirrored-fill variant of its length
+ * (names ending in "_e"), the only choice ups_plan_set_kernel accepts there. */
 int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap);
 
 /* Select the compiled variant `name` for pass 0..4 (names as returned by
@@ -295,7 +307,8 @@ double ups_plan_model_bytes(ups_plan_t plan, int pass);
  * padded length, size class), the size class being floor(log2) of the
  * number of lines the pass transforms (rows for the x passes, kx columns
  * times z planes for the y passes, kx times ky columns for the z pass,
- * times ncomp); keys read "zconv/f32/1024/l19".  With the environment
+ * times ncomp); keys read "zconv/f32/1024/l19" (with "/e" appended for a
+ * forward pass along an even or odd direction).  With the environment
  * variable UPS_TUNE_CACHE set to a file path the cache is loaded from and
  * saved to that JSON file.  Waits for the stream.  Errors: INVALID_ARG (null
  * or misaligned f or u), STATE (setup not done), DEVICE. */

@@ -58,7 +58,8 @@ std::string tune_key(PassKind kind, const PlanGeom& g) {
     ++lg;
   }
   char buf[64];
-  snprintf(buf, sizeof buf, "%s/%s/%d/l%d", kKindName[int(kind)], g.f64 ? "f64" : "f32", length, lg);
+  snprintf(buf, sizeof buf, "%s/%s/%d/l%d%s", kKindName[int(kind)], g.f64 ? "f64" : "f32", length, lg,
+           pass_fill(kind, g) ? "/e" : "");
   return buf;
 }
 
@@ -118,11 +119,12 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
     auto it = g_cache.find(tune_key(kind, g));
     if (it != g_cache.end()) name = it->second;
   }
+  const int fill = pass_fill(kind, g);
   if (!name.empty()) {
-    const PassVariant* v = find_variant(kind, f64, length, name.c_str());
+    const PassVariant* v = find_variant(kind, f64, length, name.c_str(), fill);
     if (v) return v;
   }
-  return find_variant(kind, f64, length, nullptr);
+  return find_variant(kind, f64, length, nullptr, fill);
 }
 
 }  // namespace ups
@@ -178,7 +180,9 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
   for (int k = 0; k < 5 && err == hipSuccess; ++k) {
     std::vector<const PassVariant*> cands;
     for (const PassVariant& v : pass_variants())
-      if (v.kind == kKinds[k] && v.is_f64 == (g.f64 ? 1 : 0) && v.length == len[k]) cands.push_back(&v);
+      if (v.kind == kKinds[k] && v.is_f64 == (g.f64 ? 1 : 0) && v.length == len[k] &&
+          v.fill == pass_fill(kKinds[k], g))
+        cands.push_back(&v);
     // the current choice first; a candidate replaces it only if it is faster
     // by more than the noise (1%)
     const PassVariant* best = plan->var[k];

@@ -42,14 +42,19 @@ namespace ups {
 
 ups_status set_error(ups_status s, const char* msg) { return fail(s, "%s", msg); }
 
-const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name) {
+const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name, int fill) {
   const PassVariant* best = nullptr;
   for (const PassVariant& v : pass_variants()) {
-    if (v.kind != kind || v.is_f64 != (f64 ? 1 : 0) || v.length != length) continue;
+    if (v.kind != kind || v.is_f64 != (f64 ? 1 : 0) || v.length != length || v.fill != fill) continue;
     if (name && std::strcmp(name, v.name) != 0) continue;
     if (!best) best = &v;
   }
   return best;
+}
+
+int pass_fill(PassKind kind, const PlanGeom& g) {
+  const int axis = kind == PASS_XFWD ? 0 : kind == PASS_YFWD ? 1 : kind == PASS_ZCONV ? 2 : -1;
+  return axis >= 0 && (g.bc[axis] == UPS_BC_EVEN || g.bc[axis] == UPS_BC_ODD) ? 1 : 0;
 }
 
 bool length_supported(int len, bool f64) {
@@ -70,8 +75,8 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
     }
     if (p->bc[i][0] != p->bc[i][1])
       return fail(UPS_ERR_UNSUPPORTED, "bc[%d]: both sides of an axis must carry the same condition", i);
-    if (p->bc[i][0] == UPS_BC_EVEN || p->bc[i][0] == UPS_BC_ODD)
-      return fail(UPS_ERR_UNSUPPORTED, "bc[%d]: even and odd directions are not solved", i);
+    if ((p->bc[i][0] == UPS_BC_EVEN || p->bc[i][0] == UPS_BC_ODD) && p->center != UPS_CELL)
+      return fail(UPS_ERR_UNSUPPORTED, "bc[%d]: even and odd directions mirror about cell faces (UPS_CELL)", i);
   }
   const bool any_spectral = p->bc[0][0] != UPS_BC_UNB || p->bc[1][0] != UPS_BC_UNB || p->bc[2][0] != UPS_BC_UNB;
   if (std::fabs(p->h[0] - p->h[1]) > 1e-12 * p->h[0] || std::fabs(p->h[0] - p->h[2]) > 1e-12 * p->h[0])
@@ -99,6 +104,16 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
     if (p->bc[i][0] == UPS_BC_PER && M[i] != 2 * p->n[i])
       return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: a periodic direction takes pad = 2 n = %d (or 0)", i, M[i],
                   2 * p->n[i]);
+    // an even or odd direction is extended to 2 n by its mirror image
+    const bool mirror = p->bc[i][0] == UPS_BC_EVEN || p->bc[i][0] == UPS_BC_ODD;
+    if (mirror && M[i] != 2 * p->n[i])
+      return fail(UPS_ERR_INVALID_ARG, "pad[%d] = %d: an even or odd direction takes pad = 2 n = %d (or 0)", i,
+                  M[i], 2 * p->n[i]);
+    if (mirror && i == 0 && p->n[0] % 2)
+      return fail(UPS_ERR_UNSUPPORTED, "an even or odd x direction needs an even n[0] (got %d)", p->n[0]);
+    const PassKind fwd = i == 0 ? PASS_XFWD : i == 1 ? PASS_YFWD : PASS_ZCONV;
+    if (mirror && !find_variant(fwd, p->prec == UPS_F64, M[i], nullptr, 1))
+      return fail(UPS_ERR_UNSUPPORTED, "even/odd direction %d: no mirrored-fill kernel for length %d", i, M[i]);
   }
   if (any_spectral && p->green != UPS_GREEN_LGF2)
     return fail(UPS_ERR_UNSUPPORTED, "non-unbounded directions are solved with the 7-point kernel only");
@@ -212,6 +227,10 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
   a.gz = g.gz;
   a.g_plane = (long long)g.kx * g.gz;
   a.ncomp = g.ncomp;
+  auto sign = [](int bc) { return bc == UPS_BC_EVEN ? 1 : bc == UPS_BC_ODD ? -1 : 0; };
+  a.fill_x = sign(g.bc[0]);
+  a.fill_y = sign(g.bc[1]);
+  a.fill_z = sign(g.bc[2]);
   if (green) {  // (a geometry-only PassArgs, e.g. for block counts, has no buffers)
     const char* gb = static_cast<const char*>(green);
     a.ghat = gb + g.off_ghat;
@@ -724,7 +743,7 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name) {
   if (!plan || pass < 0 || pass > 4 || !name) return fail(UPS_ERR_INVALID_ARG, "bad plan, pass or name");
   const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
   const int len[5] = {plan->g.mx, plan->g.my, plan->g.mz, plan->g.my, plan->g.mx};
-  const PassVariant* v = find_variant(kinds[pass], plan->g.f64, len[pass], name);
+  const PassVariant* v = find_variant(kinds[pass], plan->g.f64, len[pass], name, pass_fill(kinds[pass], plan->g));
   if (!v) return fail(UPS_ERR_INVALID_ARG, "no variant '%s' for pass %d at length %d", name, pass, len[pass]);
   plan->var[pass] = v;
   return ok();
@@ -735,7 +754,7 @@ int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap
   const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
   int n = 0;
   for (const PassVariant& v : pass_variants()) {
-    if (v.kind != kinds[pass] || v.is_f64 != (prec == UPS_F64 ? 1 : 0) || v.length != len) continue;
+    if (v.kind != kinds[pass] || v.is_f64 != (prec == UPS_F64 ? 1 : 0) || v.length != len || v.fill) continue;
     if (n < cap) names[n] = v.name;
     ++n;
   }

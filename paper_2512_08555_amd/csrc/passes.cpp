@@ -26,7 +26,7 @@ const PassVariant* narrow_variant(const PassVariant& v) {
   if (v.kind == PASS_XFWD || v.kind == PASS_XINV) return nullptr;
   const PassVariant* best = nullptr;
   for (const PassVariant& w : pass_variants()) {
-    if (w.kind != v.kind || w.is_f64 != v.is_f64 || w.length != v.length) continue;
+    if (w.kind != v.kind || w.is_f64 != v.is_f64 || w.length != v.length || w.fill != v.fill) continue;
     if ((w.nch == 0) != (v.nch == 0)) continue;  // same kernel family
     if (!best || w.tile < best->tile) best = &w;
   }

@@ -30,6 +30,9 @@ struct PassArgs {
   const void* tw_y;
   const void* tw_z;
   const void* ghat;
+  // even (+1) or odd (-1) direction, else 0: the forward pass along that
+  // axis fills rows n >= n_axis with +-(row 2 n_axis - 1 - n) instead of zeros
+  int fill_x, fill_y, fill_z;
 };
 
 // One problem of a grouped launch (many problems, one pass, one kernel).
@@ -67,6 +70,9 @@ struct PassVariant {
   void (*launch)(const PassArgs&, const void* in, void* out, hipStream_t);
   // enqueue one grouped launch of nblocks blocks
   void (*launch_grouped)(const GroupArgs&, unsigned nblocks, hipStream_t);
+  // 1: a forward pass for an even or odd direction (mirrored second half of
+  // the line, full first stage); the other passes and directions take 0
+  int fill;
 };
 
 const std::vector<PassVariant>& pass_variants();

@@ -39,6 +39,13 @@ std::vector<PassVariant> variants_f32_pow2() {
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),
       YI(float, 32, 32, 16, 4), YI(float, 32, 32, 4, 1), YI(float, 32, 32, 4, 2),
       YF(float, 32, 32, 2, 1), YI(float, 32, 32, 2, 1),
+      // even and odd directions, mx/my/mz = 32 .. 1024
+      FILL_VARIANTS(float, 4, 4, 16, 1, 4, 8, 16, 1, 4, 8, 16, 1),
+      FILL_VARIANTS(float, 4, 8, 16, 1, 8, 8, 16, 1, 8, 8, 16, 1),
+      FILL_VARIANTS(float, 8, 8, 16, 2, 8, 16, 16, 2, 8, 16, 16, 2),
+      FILL_VARIANTS(float, 8, 16, 16, 2, 16, 16, 16, 2, 16, 16, 16, 2),
+      FILL_VARIANTS(float, 16, 16, 16, 2, 16, 32, 16, 2, 16, 32, 16, 2),
+      FILL_VARIANTS(float, 16, 32, 4, 1, 32, 32, 16, 2, 32, 32, 8, 2),
   };
 }
 

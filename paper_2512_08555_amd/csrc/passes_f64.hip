@@ -35,6 +35,13 @@ std::vector<PassVariant> variants_f64() {
       YFW(double, 16, 4), YFW(double, 16, 1),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
       YF(double, 32, 32, 2, 1), YI(double, 32, 32, 2, 1),
+      // even and odd directions, mx/my/mz = 32 .. 1024
+      FILL_VARIANTS(double, 4, 4, 8, 1, 4, 8, 8, 1, 4, 8, 8, 1),
+      FILL_VARIANTS(double, 4, 8, 8, 1, 8, 8, 8, 1, 8, 8, 8, 1),
+      FILL_VARIANTS(double, 8, 8, 8, 2, 8, 16, 8, 2, 8, 16, 8, 2),
+      FILL_VARIANTS(double, 8, 16, 8, 2, 16, 16, 8, 2, 16, 16, 8, 2),
+      FILL_VARIANTS(double, 16, 16, 8, 2, 16, 32, 8, 2, 16, 32, 8, 2),
+      FILL_VARIANTS(double, 16, 32, 8, 2, 32, 32, 8, 2, 32, 32, 8, 2),
   };
 }
 

@@ -181,7 +181,11 @@ constexpr int xfwd_row_stride() {
   return (ys > zs ? ys : zs) | 1;
 }
 
-template <typename T, int P, int Q, int RW, int NCH>
+// FILL: an even or odd direction (a.fill_x = +1 or -1, nx = L, nx even):
+// the extended row x[2 nx - 1 - n] = +-x[n] packs to z[m] = +-swap(z[L-1-m])
+// for m >= L/2, which the threads load instead of the zero padding; the
+// first stage is then a full DFT.
+template <typename T, int P, int Q, int RW, int NCH, bool FILL = false>
 __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __restrict__ W, const PassArgs& a,
                                           unsigned bx, unsigned by) {
   using S = Split<P, Q>;
@@ -232,7 +236,19 @@ __device__ __forceinline__ void xfwd_body(const T* __restrict__ f, cx<T>* __rest
         v[d][p] = val;
       });
     }
-    first_dft<P, -1>(v[d]);
+    if constexpr (FILL) {
+      static_assert(P % 2 == 0, "mirrored rows need an even split");
+      const T sg = T(a.fill_x);
+      static_for<P / 2, P>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        const int mq = L - 1 - (q + Q * p);
+        const cx<T> zv = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * mq));
+        v[d][p] = cx<T>{sg * zv.im, sg * zv.re};
+      });
+      dft<P, -1>(v[d]);
+    } else {
+      first_dft<P, -1>(v[d]);
+    }
     const cx<T>* trow = tw_row(tw, 2 * L, unsigned(q));
     // w_L^{q k1} = w_M^{2 q k1}
     twiddle_run<P, false>(v[d], [&](int j) { return trow[2 << j]; });
@@ -415,10 +431,13 @@ __device__ __forceinline__ void xinv_body(const cx<T>* __restrict__ W, T* __rest
 // k1 = tl + TL d3.
 // TWP: a thread's twiddle run from log2 table loads and products (fewer
 // loads, more VALU) instead of one table load per twiddle.
-template <typename T, int P, int Q, int C, int NCH, bool TWP, bool NTL>
+// FILL: an even or odd direction (nlive = M/2, fill_sign = +1 or -1): rows
+// n >= M/2 are fill_sign times row M - 1 - n, loaded instead of the zero
+// padding, and the first stage is a full DFT.
+template <typename T, int P, int Q, int C, int NCH, bool TWP, bool NTL, bool FILL = false>
 __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride, int cload, int nlive,
                                             const cx<T>* tw, cx<T>* lds, int c, int tl,
-                                            ColSpec<T, P, Q>& w) {
+                                            ColSpec<T, P, Q>& w, T fill_sign = T(0)) {
   using S = Split<P, Q>;
   constexpr int TL = S::TL, CG = C / NCH;
   constexpr unsigned CB = sizeof(cx<T>);
@@ -442,7 +461,17 @@ __device__ __forceinline__ void col_forward(const cx<T>* ubase, long long stride
         v[p] = q + Q * p < nlive ? ld_at<NTL>(ubase + (long long)(Q * p) * stride, toff) : zero_c<T>();
       });
     }
-    first_dft<P, -1>(v);
+    if constexpr (FILL) {
+      static_assert(P % 2 == 0, "mirrored rows need an even split");
+      static_for<P / 2, P>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        const int mr = P * Q - 1 - (q + Q * p);  // < M/2
+        v[p] = scale(ld_at<NTL>(ubase + (long long)mr * stride, unsigned(cload) * CB), fill_sign);
+      });
+      dft<P, -1>(v);
+    } else {
+      first_dft<P, -1>(v);
+    }
     const cx<T>* trow = tw_row(tw, S::L, unsigned(q));
     if constexpr (TWP) {
       twiddle_run<P, false>(v, [&](int j) { return trow[1 << j]; });
@@ -628,7 +657,7 @@ __host__ __device__ inline unsigned zmap_blocks(int ntiles, int my, int ncomp, i
 }
 
 // Pass 2: DFT along y, rows y < ny live, all my outputs kept (in place).
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned blin) {
   using S = Split<P, Q>;
   static_assert(C % NCH == 0, "column groups");
@@ -644,7 +673,8 @@ __device__ __forceinline__ void yfwd_body(cx<T>* __restrict__ W, const PassArgs&
   cx<T>* ubase = W + comp * a.comp_w + z * a.plane + kx0;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw_y);
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH, false, nt_load<1>()>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, false, nt_load<1>(), FILL>(ubase, a.px, cload, a.ny, tw, lds, c, tl, w,
+                                                           T(a.fill_y));
   if (valid) {
     static_for<0, S::D3>([&](auto dd) {
       constexpr int d = decltype(dd)::value;
@@ -689,7 +719,7 @@ __device__ __forceinline__ void yinv_body(cx<T>* __restrict__ W, const PassArgs&
 
 // Pass 3: along z, forward DFT (z < nz live), times G_hat, inverse DFT, keep
 // z < nz; in place.  One workgroup per (column tile, ky, component).
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using S = Split<P, Q>;
   constexpr int M = S::L;
@@ -709,7 +739,8 @@ __device__ __forceinline__ void zconv_body(cx<T>* __restrict__ W, const PassArgs
   const int cload = valid ? c : a.kx - 1 - kx0;
   cx<T>* ubase = W + mp.comp * a.comp_w + (long long)ky * a.px + kx0;
   ColSpec<T, P, Q> w;
-  col_forward<T, P, Q, C, NCH, true, nt_load<2>()>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w);
+  col_forward<T, P, Q, C, NCH, true, nt_load<2>(), FILL>(ubase, a.plane, cload, a.nz, tw, lds, c, tl, w,
+                                                          T(a.fill_z));
   static_for<0, S::D3>([&](auto dd) {
     constexpr int d = decltype(dd)::value;
     const int k1 = tl + S::TL * d;
@@ -761,20 +792,20 @@ __device__ __forceinline__ void* group_out(const GroupArgs& g, const GroupEntry&
   return e.io_out >= 0 ? const_cast<void*>(g.io[e.io_out]) : e.out;
 }
 
-template <typename T, int P, int Q, int RW, int NCH>
+template <typename T, int P, int Q, int RW, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((RW * Split<P, Q>::TL))
 k_xfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
-  xfwd_body<T, P, Q, RW, NCH>(f, W, a, blockIdx.x, blockIdx.y);
+  xfwd_body<T, P, Q, RW, NCH, FILL>(f, W, a, blockIdx.x, blockIdx.y);
 }
-template <typename T, int P, int Q, int RW, int NCH>
+template <typename T, int P, int Q, int RW, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((RW * Split<P, Q>::TL)) k_xfwd_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
   const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
-  xfwd_body<T, P, Q, RW, NCH>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)), e.a,
-                              lin % gx, lin / gx);
+  xfwd_body<T, P, Q, RW, NCH, FILL>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)),
+                                    e.a, lin % gx, lin / gx);
 }
 template <typename T, int P, int Q, int RW, int NCH>
 __global__ void __launch_bounds__((RW * Split<P, Q>::TL))
@@ -791,17 +822,17 @@ __global__ void __launch_bounds__((RW * Split<P, Q>::TL)) k_xinv_g(GroupArgs g) 
   xinv_body<T, P, Q, RW, NCH>(static_cast<const cx<T>*>(group_in(g, e)), static_cast<T*>(group_out(g, e)), e.a,
                               lin % gx, lin / gx);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd(cx<T>* __restrict__ W, PassArgs a) {
-  yfwd_body<T, P, Q, C, NCH>(W, a, blockIdx.x);
+  yfwd_body<T, P, Q, C, NCH, FILL>(W, a, blockIdx.x);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yfwd_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  yfwd_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  yfwd_body<T, P, Q, C, NCH, FILL>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 template <typename T, int P, int Q, int C, int NCH>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv(cx<T>* __restrict__ W, PassArgs a) {
@@ -815,23 +846,23 @@ __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_yinv_g(GroupArgs g) {
   if (!live) return;  // uniform over the workgroup, before any barrier
   yinv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_zconv(cx<T>* __restrict__ W, PassArgs a) {
-  zconv_body<T, P, Q, C, NCH>(W, a, blockIdx.x);
+  zconv_body<T, P, Q, C, NCH, FILL>(W, a, blockIdx.x);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 __global__ void __launch_bounds__((C * Split<P, Q>::TL)) k_zconv_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  zconv_body<T, P, Q, C, NCH>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  zconv_body<T, P, Q, C, NCH, FILL>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 
-template <typename T, int P, int Q, int RW, int NCH>
+template <typename T, int P, int Q, int RW, int NCH, bool FILL = false>
 void launch_xfwd(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
-  hipLaunchKernelGGL((k_xfwd<T, P, Q, RW, NCH>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
+  hipLaunchKernelGGL((k_xfwd<T, P, Q, RW, NCH, FILL>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
                      static_cast<const T*>(in), static_cast<cx<T>*>(out), a);
 }
 template <typename T, int P, int Q, int RW, int NCH>
@@ -840,31 +871,37 @@ void launch_xinv(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   hipLaunchKernelGGL((k_xinv<T, P, Q, RW, NCH>), grid, dim3(RW * Split<P, Q>::TL), 0, s,
                      static_cast<const cx<T>*>(in), static_cast<T*>(out), a);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 void launch_yfwd(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_yfwd<T, P, Q, C, NCH>), dim3(ypass_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
-                     static_cast<cx<T>*>(out), a);
+  hipLaunchKernelGGL((k_yfwd<T, P, Q, C, NCH, FILL>), dim3(ypass_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0,
+                     s, static_cast<cx<T>*>(out), a);
 }
 template <typename T, int P, int Q, int C, int NCH>
 void launch_yinv(const PassArgs& a, const void*, void* out, hipStream_t s) {
   hipLaunchKernelGGL((k_yinv<T, P, Q, C, NCH>), dim3(ypass_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int P, int Q, int C, int NCH>
+template <typename T, int P, int Q, int C, int NCH, bool FILL = false>
 void launch_zconv(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH>), dim3(zconv_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0, s,
-                     static_cast<cx<T>*>(out), a);
+  hipLaunchKernelGGL((k_zconv<T, P, Q, C, NCH, FILL>), dim3(zconv_blocks<T, C>(a)), dim3(C * Split<P, Q>::TL), 0,
+                     s, static_cast<cx<T>*>(out), a);
 }
 #define UPS_GROUPED_LAUNCHER(kname)                                                                   \
   template <typename T, int P, int Q, int B, int NCH>                                                  \
   void launchg_##kname(const GroupArgs& g, unsigned nblocks, hipStream_t s) {                         \
     hipLaunchKernelGGL((k_##kname##_g<T, P, Q, B, NCH>), dim3(nblocks), dim3(B * Split<P, Q>::TL), 0, s, g); \
   }
-UPS_GROUPED_LAUNCHER(xfwd)
+#define UPS_GROUPED_LAUNCHER_FILL(kname)                                                              \
+  template <typename T, int P, int Q, int B, int NCH, bool FILL = false>                               \
+  void launchg_##kname(const GroupArgs& g, unsigned nblocks, hipStream_t s) {                         \
+    hipLaunchKernelGGL((k_##kname##_g<T, P, Q, B, NCH, FILL>), dim3(nblocks), dim3(B * Split<P, Q>::TL), 0, s, \
+                       g);                                                                             \
+  }
+UPS_GROUPED_LAUNCHER_FILL(xfwd)
 UPS_GROUPED_LAUNCHER(xinv)
-UPS_GROUPED_LAUNCHER(yfwd)
+UPS_GROUPED_LAUNCHER_FILL(yfwd)
 UPS_GROUPED_LAUNCHER(yinv)
-UPS_GROUPED_LAUNCHER(zconv)
+UPS_GROUPED_LAUNCHER_FILL(zconv)
 
 template <typename T>
 constexpr int is64() { return sizeof(T) == 8 ? 1 : 0; }
@@ -889,6 +926,23 @@ constexpr int is64() { return sizeof(T) == 8 ? 1 : 0; }
 #define COL_VARIANTS(T, P, Q, C, NCH)                                                          \
   COL_VARIANT(PASS_YFWD, yfwd, T, P, Q, C, NCH), COL_VARIANT(PASS_ZCONV, zconv, T, P, Q, C, NCH), \
       COL_VARIANT(PASS_YINV, yinv, T, P, Q, C, NCH)
+
+// Forward passes for even and odd directions (mirrored second half, full
+// first stage): one per padded length, named with the suffix "_e".
+#define XF_FILL(T, P, Q, RW, NCH)                                                              \
+  PassVariant{PASS_XFWD, is64<T>(), 2 * P * Q, P, Q, RW, NCH, RW * Split<P, Q>::TL,            \
+              int(sizeof(cx<T>)) * (RW / NCH) * xfwd_row_stride<P, Q>(),                        \
+              "xfwd_" #T "_" #P "x" #Q "_r" #RW "_h" #NCH "_e", &launch_xfwd<T, P, Q, RW, NCH, true>, \
+              &launchg_xfwd<T, P, Q, RW, NCH, true>, 1}
+#define COL_FILL(KIND, kname, T, P, Q, C, NCH)                                                 \
+  PassVariant{KIND, is64<T>(), P * Q, P, Q, C, NCH, C * Split<P, Q>::TL,                       \
+              int(sizeof(cx<T>)) * col_lds_elems<P, Q, C, NCH>(),                               \
+              #kname "_" #T "_" #P "x" #Q "_c" #C "_h" #NCH "_e", &launch_##kname<T, P, Q, C, NCH, true>, \
+              &launchg_##kname<T, P, Q, C, NCH, true>, 1}
+#define YF_FILL(T, P, Q, C, NCH) COL_FILL(PASS_YFWD, yfwd, T, P, Q, C, NCH)
+#define ZC_FILL(T, P, Q, C, NCH) COL_FILL(PASS_ZCONV, zconv, T, P, Q, C, NCH)
+#define FILL_VARIANTS(T, XP, XQ, XRW, XNCH, YP, YQ, YC, YNCH, ZP, ZQ, ZC, ZNCH) \
+  XF_FILL(T, XP, XQ, XRW, XNCH), YF_FILL(T, YP, YQ, YC, YNCH), ZC_FILL(T, ZP, ZQ, ZC, ZNCH)
 
 #define XF(T, P, Q, RW, NCH) XF_VARIANT(T, P, Q, RW, NCH)
 #define XI(T, P, Q, RW, NCH) XI_VARIANT(T, P, Q, RW, NCH)

@@ -31,7 +31,11 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g);
 // guards: lay out canary bands around W in the work buffer (guard mode)
 void plan_layout(PlanGeom& g, bool guards = false);
 double model_bytes(const PlanGeom& g, int pass);
-const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name);
+// fill: 1 for the mirrored-fill forward variants of even and odd directions
+const PassVariant* find_variant(PassKind kind, bool f64, int length, const char* name, int fill = 0);
+// 1 if pass `kind` runs along an even or odd direction of g and needs a
+// mirrored-fill variant, else 0
+int pass_fill(PassKind kind, const PlanGeom& g);
 const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom& g);
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);

@@ -88,8 +88,21 @@ def test_validation_errors():
     assert s == capi.UPS_ERR_INVALID_ARG and "periodic" in msg
     for b in ("even", "odd"):
         p = make_problem((32, 32, 32), 1 / 32, bc=("unb", b, "unb"))
+        s, h, _ = _create(p)
+        assert s == capi.UPS_OK
+        assert L.ups_plan_kernel(h, 1).decode().endswith("_e")        # mirrored-fill y-forward
+        assert not L.ups_plan_kernel(h, 3).decode().endswith("_e")    # inverse unchanged
+        L.ups_plan_destroy(h)
+        p = make_problem((32, 32, 32), 1 / 32, bc=("unb", b, "unb"))
+        p.center = capi.UPS_NODE
         s, _, msg = _create(p)
-        assert s == capi.UPS_ERR_UNSUPPORTED and "even and odd" in msg
+        assert s == capi.UPS_ERR_UNSUPPORTED and "cell faces" in msg
+    p = make_problem((32, 32, 31), 1 / 32, pad=(64, 64, 62), bc=("unb", "unb", "even"))
+    s, _, msg = _create(p)
+    assert s == capi.UPS_ERR_UNSUPPORTED and "even n[0]" in msg
+    p = make_problem((32, 32, 40), 1 / 40, bc=("unb", "unb", "odd"))   # 80: no mirrored-fill kernel
+    s, _, msg = _create(p)
+    assert s == capi.UPS_ERR_UNSUPPORTED and "mirrored-fill" in msg
     p = make_problem((32, 32, 32), 1 / 32, bc=("per", "unb", "unb"))
     p.green = capi.UPS_GREEN_LGF4_MEHR
     assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED

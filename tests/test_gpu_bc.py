@@ -1,5 +1,6 @@
-"""Periodic directions mixed with unbounded ones (Sec. 2.2, eq. 2unbkernel)
-through the C ABI, against the oracle's plain per-axis solve."""
+"""Periodic, even and odd directions mixed with unbounded ones (Sec. 2.2,
+eq. 2unbkernel) through the C ABI, against the oracle's plain per-axis
+solve."""
 import itertools
 
 import numpy as np
@@ -22,10 +23,10 @@ def _rel_inf(a, b):
 
 
 def _pads(shape, bc, prec):
-    """2 n along periodic axes, the smallest supported length >= 2 n along
-    unbounded ones."""
+    """2 n along periodic, even and odd axes, the smallest supported length
+    >= 2 n along unbounded ones."""
     ap = auto_pad(shape, prec)
-    return tuple(2 * n if b == "per" else m for n, b, m in zip(shape, bc, ap))
+    return tuple(m if b == "unb" else 2 * n for n, b, m in zip(shape, bc, ap))
 
 
 def _source(shape, h, seed):
@@ -104,3 +105,81 @@ def test_batch_with_periodic_directions_equals_single_plans():
         assert torch.equal(p.solve(fs[i]), us[i]), i
         ref = obc.solve_bc(fs[i].double().cpu().numpy(), sp["h"], sp["bc"], M=sp["pad"])
         assert _rel_inf(us[i].double().cpu().numpy(), ref) < TOL["f32"], i
+
+
+# ---- even and odd directions (mirrored fill in the forward passes) ----------------
+
+MIRROR = [("even", "unb", "unb"), ("unb", "odd", "unb"), ("unb", "unb", "even"), ("odd", "odd", "odd"),
+          ("even", "even", "even"), ("per", "even", "odd"), ("odd", "unb", "per"), ("even", "odd", "unb")]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bc", MIRROR)
+def test_even_odd_mixes_match_oracle(bc, prec):
+    # spectral axes of 16 or 32 points (the mirrored-fill kernels cover
+    # padded lengths 32 .. 1024); the x extent of an even or odd direction
+    # must be even
+    base = (20, 27, 13)
+    shape = tuple(n if b == "unb" else (32 if i == 1 else 16) for i, (b, n) in enumerate(zip(bc, base)))
+    f_mean_free = "unb" not in bc and "odd" not in bc
+    h = 1.0 / max(shape)
+    pad = _pads(shape, bc, prec)
+    print("[case] bc %s %s shape %s pad %s" % (bc, prec, shape, pad), flush=True)
+    f = _source(shape, h, 17 + hash(bc) % 91)
+    if f_mean_free:
+        f -= f.mean()
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    plan = Plan(shape, h, prec, pad=pad, bc=bc)
+    assert all(plan.kernel(k).endswith("_e") == (bc[2 - k] in ("even", "odd")) for k in range(3))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    ref = obc.solve_bc(f, h, bc, M=pad)
+    err = _rel_inf(u, ref)
+    print("  rel Linf %.3e" % err, flush=True)
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_even_odd_at_long_lines(prec):
+    # mirrored fill at the lengths 512 and 1024 (the four-step kernels)
+    shape, bc = (64, 16, 512), ("even", "odd", "even")
+    h = 1.0 / 512
+    pad = _pads(shape, bc, prec)
+    print("[case] bc %s %s shape %s pad %s" % (bc, prec, shape, pad), flush=True)
+    f = _source(shape, h, 77)
+    f -= f.mean()
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    plan = Plan(shape, h, prec, pad=pad, bc=bc)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    ref = obc.solve_bc(f, h, bc, M=pad)
+    assert _rel_inf(u, ref) < TOL[prec]
+    shape, bc = (256, 24, 20), ("odd", "unb", "unb")
+    h = 1.0 / 256
+    pad = _pads(shape, bc, prec)
+    print("[case] bc %s %s shape %s pad %s" % (bc, prec, shape, pad), flush=True)
+    f = _source(shape, h, 78)
+    if prec == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    plan = Plan(shape, h, prec, pad=pad, bc=bc)
+    u = plan.solve(torch.from_numpy(f).to("cuda", dt)).double().cpu().numpy()
+    ref = obc.solve_bc(f, h, bc, M=pad)
+    assert _rel_inf(u, ref) < TOL[prec]
+
+
+def test_batch_with_even_and_odd_directions_equals_single_plans():
+    specs = [dict(shape=(32, 20, 16), h=1 / 32, prec="f64", bc=("even", "unb", "odd"), pad=(64, 64, 32)),
+             dict(shape=(16, 16, 16), h=1 / 16, prec="f64", bc=("odd",) * 3, pad=(32, 32, 32)),
+             dict(shape=(24, 20, 16), h=1 / 24, prec="f64", pad=(64, 64, 32))]
+    print("[case] batch of %d problems with even and odd directions" % len(specs), flush=True)
+    b = Batch(specs)
+    fs = [torch.from_numpy(_source(sp["shape"], sp["h"], 60 + i)).cuda() for i, sp in enumerate(specs)]
+    us = b.solve(fs)
+    torch.cuda.synchronize()
+    for i, sp in enumerate(b.specs):
+        p = Plan(sp["shape"], sp["h"], "f64", pad=sp["pad"], bc=sp["bc"])
+        assert torch.equal(p.solve(fs[i]), us[i]), i
+        ref = obc.solve_bc(fs[i].cpu().numpy(), sp["h"], sp["bc"], M=sp["pad"])
+        assert _rel_inf(us[i].cpu().numpy(), ref) < TOL["f64"], i
