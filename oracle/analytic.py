@@ -10,6 +10,11 @@ only (see ``oracle/__init__.py``).
   u_ref = u_unb(x) u_unb(y) u_unb(z), u_unb(x) = exp[10 (1 - 1/(1 - (2x-1)^2))]
   on (0, 1) and 0 outside, with f = Lap u_ref.  Because u_ref has compact
   support, it *is* the free-space solution for that f.
+* The compact vortex tube of Sec. 5 (unbounded in x and y, periodic in z):
+  u = (-sin(theta) u_theta, cos(theta) u_theta, 0) about the axis
+  x = y = 1/2, u_theta(r) = (1/(2 pi r)) [1 - (1 - (r/R)^2) E_2(1/(1 - (r/R)^2))
+  / E_2(1)] inside the tube and 1/(2 pi r) outside: the velocity whose
+  Laplacian is -curl(omega e_z) for the tube's vorticity (unit circulation).
 """
 
 from math import pi
@@ -75,3 +80,22 @@ def bump_source(x, y, z):
     return (uz[:, None, None] * uy[None, :, None] * dx[None, None, :]
             + uz[:, None, None] * dy[None, :, None] * ux[None, None, :]
             + dz[:, None, None] * uy[None, :, None] * ux[None, None, :])
+
+
+def vortex_tube_velocity(n, R=0.3, nz=None):
+    """u of the vortex tube on the cell-centred grid (n cells in x and y,
+    nz along z, h = 1/n): array [3][nz][n][n], components (x, y, z)."""
+    n = int(n)
+    nz = n if nz is None else int(nz)
+    x = (np.arange(n) + 0.5) / n - 0.5
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    r = np.sqrt(X * X + Y * Y)
+    q = (r / R) ** 2
+    ut = 1.0 / (2.0 * pi * r)
+    inside = q < 1.0
+    a = 1.0 - q[inside]
+    ut[inside] *= 1.0 - a * special.expn(2, 1.0 / a) / special.expn(2, 1.0)
+    u = np.zeros((3, nz, n, n))
+    u[0] = (-(Y / r) * ut)[None]
+    u[1] = ((X / r) * ut)[None]
+    return u

@@ -17,9 +17,14 @@ Recipes (Gaussian blobs follow the paper's exp(-|x - c|^2 / sigma^2) form):
   g_b = exp(-|x - c_b|^2 / sigma_b^2); evaluated analytically as
   curl(a g) = grad(g) x a.
 * ``weight``: w = exp(0.5 sum_b s_b g_b), signs s_b = +-1.
+* ``vortex_tube``: the paper's compact vortex tube along z (Sec. 5),
+  omega_z(r) = (1/2pi) (2/R^2) exp(-1/(1 - (r/R)^2)) / E_2(1) for r < R about
+  the axis x = y = 1/2, and the Biot-Savart source f = -curl(omega e_z) =
+  (-d omega/dy, d omega/dx, 0), evaluated analytically.
 """
 
 import numpy as np
+from scipy import special
 
 
 def cell_centres(n, h):
@@ -155,3 +160,28 @@ def config_c5(n=256):
     h = 1.0 / n
     return dict(name="c5", shape=(n, n, n), h=h, prec="f32",
                 f=config_blobs_noise(n, 5), w=weight_field(n, h, seed=55))
+
+
+def vortex_tube_source(n, R=0.3, nz=None):
+    """-curl(omega_z e_z) for the vortex tube of radius R on the unit square
+    in x and y (n cells each) and nz cells along z (default n, h = 1/n):
+    array [3][nz][n][n] with components (x, y, z).  The tube does not
+    depend on z."""
+    n = int(n)
+    nz = n if nz is None else int(nz)
+    h = 1.0 / n
+    x = cell_centres(n, h) - 0.5
+    X, Y = np.meshgrid(x, x, indexing="xy")          # [y][x]
+    q = (X * X + Y * Y) / (R * R)
+    inside = q < 1.0
+    c0 = 1.0 / (2.0 * np.pi) * 2.0 / (R * R) / special.expn(2, 1.0)
+    om = np.zeros_like(q)
+    om[inside] = c0 * np.exp(-1.0 / (1.0 - q[inside]))
+    dg = np.zeros_like(q)                              # d/d(r^2) of -1/(1 - r^2/R^2), times 2
+    dg[inside] = -2.0 / (R * R * (1.0 - q[inside]) ** 2)
+    fx = -(om * dg * Y)                                # -d omega/dy
+    fy = om * dg * X                                   # d omega/dx
+    f = np.zeros((3, nz, n, n))
+    f[0] = fx[None]
+    f[1] = fy[None]
+    return f

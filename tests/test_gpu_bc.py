@@ -183,3 +183,25 @@ def test_batch_with_even_and_odd_directions_equals_single_plans():
         assert torch.equal(p.solve(fs[i]), us[i]), i
         ref = obc.solve_bc(fs[i].cpu().numpy(), sp["h"], sp["bc"], M=sp["pad"])
         assert _rel_inf(us[i].cpu().numpy(), ref) < TOL["f64"], i
+
+
+def test_vortex_tube_velocity_second_order():
+    # the paper's Biot-Savart benchmark (Sec. 5): -curl(omega) as a
+    # 3-component source, unbounded in x and y, periodic in z; FP64 against
+    # the oracle at 32^3 and against the closed-form velocity at second order
+    from oracle import analytic
+    errs = []
+    for n in (32, 64, 128):
+        print("[case] vortex tube %d^3 f64" % n, flush=True)
+        f = workloads.vortex_tube_source(n)
+        plan = Plan((n, n, n), 1.0 / n, "f64", ncomp=3, bc=("per", "unb", "unb"))
+        u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+        assert np.abs(u[2]).max() < 1e-12 * np.abs(u[:2]).max()
+        ref = analytic.vortex_tube_velocity(n)
+        errs.append(np.abs(u[:2] - ref[:2]).max() / np.abs(ref[:2]).max())
+        if n == 32:
+            for c in range(2):
+                assert _rel_inf(u[c], obc.solve_bc(f[c], 1.0 / n, ("per", "unb", "unb"))) < 1e-12
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print("vortex tube rel Linf %s orders %s" % (errs, orders), flush=True)
+    assert 1.95 < orders[-1] < 2.2 and errs[-1] < 5e-4
