@@ -22,6 +22,10 @@ multiresolution grids"):
                   periodic, even, odd; Sec. 2.2 and eq. 2unbkernel), by one
                   plain transform per axis, and the lower-dimensional lattice
                   Green's functions it needs.
+* ``mehrstellen`` -- the fourth- and sixth-order Mehrstellen pairs (eqs.
+                  mehrstellen_discr4/6): the LGF of L by the 7-point LGF plus
+                  a graded quadrature of the bounded difference of the inverse
+                  symbols, the kernel R G_L, and the solve with it.
 * ``analytic`` -- closed forms used as pins: Watson's constant, the Gaussian
                   charge potential, the paper's compact manufactured solution
                   (Sec. 4.2, unbounded domains).
@@ -34,12 +38,12 @@ from .lgf import (watson_g0, lgf_table, lgf_point_adaptive, lgf_far_field,
 from .spectrum import green_spectrum_raw, green_spectrum_rfft, green_spectrum_scaled
 from .solve import (solve, solve_full, brute_force, brute_force_adjoint,
                     adjoint, laplacian7_interior)
-from . import analytic, bc
+from . import analytic, bc, mehrstellen
 
 __all__ = [
     "watson_g0", "lgf_table", "lgf_point_adaptive", "lgf_far_field", "lgf_tail",
     "quadrature_nodes", "hankel_coefficients",
     "green_spectrum_raw", "green_spectrum_rfft", "green_spectrum_scaled",
     "solve", "solve_full", "brute_force", "brute_force_adjoint", "adjoint",
-    "laplacian7_interior", "analytic", "bc",
+    "laplacian7_interior", "analytic", "bc", "mehrstellen",
 ]
