@@ -85,8 +85,14 @@ typedef enum { UPS_BC_UNB = 0, UPS_BC_PER = 1, UPS_BC_EVEN = 2, UPS_BC_ODD = 3 }
 
 /* Green's kernel: the LGF of the operator the caller discretises with
  * (Sec. 3.3).  UPS_GREEN_LGF2 = LGF of the 7-point stencil (eq. cross_discr2).
- * The Mehrstellen kernels of eq. mehrstellen_discr4 / _discr6 are reserved
- * and return UPS_ERR_UNSUPPORTED. */
+ * UPS_GREEN_LGF4_MEHR / _LGF6_MEHR: the compact Mehrstellen pairs of eqs.
+ * mehrstellen_discr4 / _discr6 (Sec. 3.2), (1/h^2) L u = R f with the
+ * 19- or 27-point L and the right-hand-side stencil R (the printed
+ * "delta_y delta_z^2" of R6 read as the symmetric d2_y d2_z): the solve
+ * applies K = R G_L, G_L the LGF of L, to f -- the same as G_L applied to
+ * R f for a source that vanishes outside the box -- so the correction of
+ * the right-hand side costs nothing at solve time.  All six sides
+ * unbounded, padded lengths up to 1024. */
 typedef enum { UPS_GREEN_LGF2 = 0, UPS_GREEN_LGF4_MEHR = 1, UPS_GREEN_LGF6_MEHR = 2 } ups_green;
 
 /* Arithmetic of the FFT stages.  UPS_F32 uses float data, float twiddles and a
@@ -134,8 +140,9 @@ void ups_problem_init(ups_problem* p);
  * 2 n or odd, pad other than 2 n along a periodic, even or odd axis),
  * UNSUPPORTED (the two sides of an axis differ, an even or odd direction
  * node-centred, of odd extent along x or without a mirrored-fill kernel,
- * Mehrstellen kernel, anisotropic h, n > 4096, padded length without a
- * compiled kernel, per-lane offsets that would not fit 32 bits). */
+ * a Mehrstellen kernel with a non-unbounded direction or a padded length
+ * above 1024, anisotropic h, n > 4096, padded length without a compiled
+ * kernel, per-lane offsets that would not fit 32 bits). */
 ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out);
 
 /* Bytes the caller must provide: green = G_hat octant plus twiddle tables,
@@ -153,7 +160,12 @@ ups_status ups_plan_sizes(ups_plan_t plan, size_t* green_bytes, size_t* work_byt
  * frequencies and zero at odd ones -- the spectrum of the n-periodic kernel
  * truncated to |d| < n, which the zero-padded convolution applies exactly;
  * along an even or odd axis the 2n-periodic spectrum itself (the forward
- * pass fills the second half of the line with the mirror image).
+ * pass fills the second half of the line with the mirror image).  With a
+ * Mehrstellen kernel: G_L = G1 + D on the octant extended by the radius
+ * of R, D the integral of the bounded (sigma_2 - sigma_L) / (sigma_L
+ * sigma_2) over the Brillouin zone by a tensor Gauss-Legendre rule graded
+ * towards k = 0 (three GEMM contractions), then R G_L, its DCT-I, and the
+ * same scaling (about 0.4 s at 512^3).
  * Enqueued on `stream`, then the host waits for it.
  * The buffers must stay alive and unchanged (green) for every later solve.
  * Errors: INVALID_ARG (null or misaligned pointers), WORKSPACE (sizes smaller

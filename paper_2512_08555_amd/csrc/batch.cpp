@@ -201,7 +201,7 @@ ups_status ups_batch_setup(ups_batch_t b, void* green, size_t green_bytes, void*
     e = build_twiddles(g.f64, g.mx, pg + g.off_twx, wb, st);
     if (e == hipSuccess) e = build_twiddles(g.f64, g.my, pg + g.off_twy, wb, st);
     if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, pg + g.off_twz, wb, st);
-    if (e == hipSuccess) e = build_green(g.f64, g.bc, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, pg + g.off_ghat, wb, st);
+    if (e == hipSuccess) e = build_green(g.f64, g.bc, g.green, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, pg + g.off_ghat, wb, st);
   }
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   // descriptor tables

@@ -83,8 +83,7 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
     return fail(UPS_ERR_UNSUPPORTED, "anisotropic spacing is not supported (h must be equal)");
   if (p->green < UPS_GREEN_LGF2 || p->green > UPS_GREEN_LGF6_MEHR)
     return fail(UPS_ERR_INVALID_ARG, "green = %d is not a ups_green", p->green);
-  if (p->green != UPS_GREEN_LGF2)
-    return fail(UPS_ERR_UNSUPPORTED, "only the 7-point LGF kernel (UPS_GREEN_LGF2) is built");
+
   if (p->prec != UPS_F64 && p->prec != UPS_F32) return fail(UPS_ERR_INVALID_ARG, "prec = %d", p->prec);
   if (p->center != UPS_CELL && p->center != UPS_NODE)
     return fail(UPS_ERR_INVALID_ARG, "center = %d", p->center);
@@ -117,6 +116,8 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   }
   if (any_spectral && p->green != UPS_GREEN_LGF2)
     return fail(UPS_ERR_UNSUPPORTED, "non-unbounded directions are solved with the 7-point kernel only");
+  if (p->green != UPS_GREEN_LGF2 && (M[0] > 1024 || M[1] > 1024 || M[2] > 1024))
+    return fail(UPS_ERR_UNSUPPORTED, "Mehrstellen kernels are built for padded lengths up to 1024");
   for (int i = 0; i < 3; ++i) {
     if (!length_supported(M[i], f64))
       return fail(UPS_ERR_UNSUPPORTED, "padded length %d (axis %d) has no compiled %s kernel", M[i], i,
@@ -138,6 +139,7 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   g->ncomp = p->ncomp;
   g->h = p->h[0];
   for (int i = 0; i < 3; ++i) g->bc[i] = p->bc[i][0];
+  g->green = p->green;
   // Every kernel addresses W as a wave-uniform 64-bit base plus a 32-bit
   // per-lane byte offset of at most 64 line strides (a row of a 64-row
   // block or of a split factor <= 64) plus a tile column; the longest line
@@ -156,9 +158,11 @@ void plan_layout(PlanGeom& g, bool guards) {
   g.comp_w = (long long)g.nz * g.plane;
   g.solve_work = align_up(ce * (size_t)g.comp_w * g.ncomp, 256);
   g.guard = guards ? kGuardBytes : 0;
-  const GreenScratch gs = green_scratch_layout(g.oz, g.oy, g.kx);
+  const size_t gbytes = g.green == UPS_GREEN_LGF2
+                            ? green_scratch_layout(g.oz, g.oy, g.kx).bytes
+                            : mehr_scratch_layout(g.oz, g.oy, g.kx, g.green == UPS_GREEN_LGF4_MEHR ? 4 : 6).bytes;
   const int mmax = std::max(g.mx, std::max(g.my, g.mz));
-  const size_t setup = std::max(gs.bytes, align_up(sizeof(double) * 2 * twiddle_entries(mmax), 256));
+  const size_t setup = std::max(gbytes, align_up(sizeof(double) * 2 * twiddle_entries(mmax), 256));
   g.work_bytes = std::max(g.solve_work + 2 * g.guard, setup);
   size_t off = 0;
   g.off_ghat = off;
@@ -511,7 +515,8 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   if (e == hipSuccess) e = build_twiddles(g.f64, g.my, gb + g.off_twy, work, st);
   if (e == hipSuccess) e = build_twiddles(g.f64, g.mz, gb + g.off_twz, work, st);
   if (e == hipSuccess)
-    e = build_green(g.f64, g.bc, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work, st);
+    e = build_green(g.f64, g.bc, g.green, g.oz, g.oy, g.kx, g.gz, g.h, g.mx, g.my, g.mz, gb + g.off_ghat, work,
+                    st);
   if (e == hipSuccess) e = enqueue_set_word(reinterpret_cast<unsigned*>(gb + g.off_status), 0u, st);
   if (e == hipSuccess && g.guard) {
     // canary bands below and above W (the Green's build used them as scratch)

@@ -285,27 +285,17 @@ GreenScratch green_scratch_layout(int kz, int ky, int kx) {
     if (e_ != hipSuccess) return e_;               \
   } while (0)
 
-template <typename T>
-hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int my, int mz, void* ghat,
-                         void* scratch, hipStream_t st) {
-  const GreenScratch L = green_scratch_layout(kz, ky, kx);
-  char* base = static_cast<char*>(scratch);
+// S = -G1 on the octant kz x ky x kx into L.off_G0 (layout L of these
+// extents).  The host vectors must stay alive until the stream is synchronised.
+static hipError_t lgf7_octant(int kz, int ky, int kx, const GreenScratch& L, char* base, std::vector<double>& t,
+                              std::vector<double>& w, hipStream_t st) {
   auto P = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
   const int kmax = std::max(kz, std::max(ky, kx));
-  std::vector<double> t, w;
   double Tsplit;
   lgf_quadrature(kmax - 1, t, w, &Tsplit);
   const int J = L.J, cols = L.cols;
   GCHECK(hipMemcpyAsync(P(L.off_t), t.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
   GCHECK(hipMemcpyAsync(P(L.off_w), w.data(), sizeof(double) * J, hipMemcpyHostToDevice, st));
-  std::vector<double> Cx, Cy, Cz;
-  cosine_matrix(kx, Cx);
-  cosine_matrix(ky, Cy);
-  cosine_matrix(kz, Cz);
-  GCHECK(hipMemcpyAsync(P(L.off_Cx), Cx.data(), sizeof(double) * Cx.size(), hipMemcpyHostToDevice, st));
-  GCHECK(hipMemcpyAsync(P(L.off_Cy), Cy.data(), sizeof(double) * Cy.size(), hipMemcpyHostToDevice, st));
-  GCHECK(hipMemcpyAsync(P(L.off_Cz), Cz.data(), sizeof(double) * Cz.size(), hipMemcpyHostToDevice, st));
-
   hipLaunchKernelGGL(k_bessel_ive, dim3((J + 63) / 64), dim3(64), 0, st, P(L.off_t), J, kmax, P(L.off_B));
   GCHECK(hipGetLastError());
   const int ext[3] = {kz, ky, kx};
@@ -317,12 +307,26 @@ hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int m
     GCHECK(hipGetLastError());
   }
   // S[nz][ny][nx] = sum_col Az[nz][col] Ay[ny][col] Ax[nx][col] -> G0 (= -G1)
-  {
-    dim3 grid((kx + GT - 1) / GT, (ky + GT - 1) / GT, kz);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Ay), ky, P(L.off_Ax), kx, cols,
-                       P(L.off_Az), (long long)cols, 1.0, P(L.off_G0), (long long)ky * kx);
-    GCHECK(hipGetLastError());
-  }
+  dim3 grid((kx + GT - 1) / GT, (ky + GT - 1) / GT, kz);
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, P(L.off_Ay), ky, P(L.off_Ax), kx, cols, P(L.off_Az),
+                     (long long)cols, 1.0, P(L.off_G0), (long long)ky * kx);
+  GCHECK(hipGetLastError());
+  return hipSuccess;
+}
+
+// G_hat[iy][kx][iz] = scale * DCT-I (three axes) of the octant table
+// [kz][ky][kx] held at L.off_G0 (L.off_G1 is the second buffer).
+template <typename T>
+static hipError_t dct3_store(int kz, int ky, int kx, int gz, double scale, const GreenScratch& L, char* base,
+                             std::vector<double>& Cx, std::vector<double>& Cy, std::vector<double>& Cz, void* ghat,
+                             hipStream_t st) {
+  auto P = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  cosine_matrix(kx, Cx);
+  cosine_matrix(ky, Cy);
+  cosine_matrix(kz, Cz);
+  GCHECK(hipMemcpyAsync(P(L.off_Cx), Cx.data(), sizeof(double) * Cx.size(), hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(L.off_Cy), Cy.data(), sizeof(double) * Cy.size(), hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(L.off_Cz), Cz.data(), sizeof(double) * Cz.size(), hipMemcpyHostToDevice, st));
   // DCT-I along x: out[kx'][nz][ny] = sum_n Cx[kx'][n] G0[(nz,ny)][n]
   {
     const int a = kz * ky;
@@ -347,14 +351,23 @@ hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int m
                        (const double*)nullptr, 0LL, 1.0, P(L.off_G1), 0LL);
     GCHECK(hipGetLastError());
   }
+  const long long tot = (long long)kz * ky * kx;
+  hipLaunchKernelGGL((k_store_ghat<T>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, P(L.off_G1), kz,
+                     ky, kx, gz, scale, static_cast<T*>(ghat));
+  GCHECK(hipGetLastError());
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t build_green_t(int kz, int ky, int kx, int gz, double h, int mx, int my, int mz, void* ghat,
+                         void* scratch, hipStream_t st) {
+  const GreenScratch L = green_scratch_layout(kz, ky, kx);
+  char* base = static_cast<char*>(scratch);
+  std::vector<double> t, w, Cx, Cy, Cz;  // host data of the asynchronous copies
+  GCHECK(lgf7_octant(kz, ky, kx, L, base, t, w, st));
   // G_hat = -(h^2 / (mx my mz)) * DCT(S)
-  {
-    const double scale = -(h * h) / (double(mx) * double(my) * double(mz));
-    const long long tot = (long long)kz * ky * kx;
-    hipLaunchKernelGGL((k_store_ghat<T>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
-                       P(L.off_G1), kz, ky, kx, gz, scale, static_cast<T*>(ghat));
-    GCHECK(hipGetLastError());
-  }
+  GCHECK(dct3_store<T>(kz, ky, kx, gz, -(h * h) / (double(mx) * double(my) * double(mz)), L, base, Cx, Cy, Cz,
+                       ghat, st));
   // the host vectors above must outlive the copies
   return hipStreamSynchronize(st);
 }
@@ -548,6 +561,316 @@ hipError_t build_green_mixed_t(const int bc[3], int kz, int ky, int kx, int gz, 
   return hipStreamSynchronize(st);
 }
 
+// ---------------------------------------------------------------------------
+// Mehrstellen kernels (eqs. mehrstellen_discr4 / _discr6, Sec. 3.2).  With
+// s_i = 4 sin^2(k_i / 2) the operator L has the symbol -sigma_L,
+//   sigma_4 = sum s - (1/6) sum_{i<j} s_i s_j,  sigma_6 = sigma_4 + (1/30) s_x s_y s_z,
+// and the right-hand-side stencil R is
+//   R_4 = 1 + (1/12) sum d2,  R_6 = R_4 + (1/90) sum_{i<j} d2_i d2_j - (1/240) sum d2_i^2
+// (the printed "delta_y delta_z^2" of R_6 taken as d2_y d2_z).  For a source
+// that vanishes outside the box, u = h^2 G_L * (R f) = h^2 (R G_L) * f, so the
+// kernel K = R G_L goes through the unchanged solve.  G_L = G1 + D with
+//   D[n] = -(1/pi^3) \int_{[0,pi]^3} prod cos(n_i k_i) (sigma_2 - sigma_L) / (sigma_L sigma_2) dk,
+// a bounded integrand (sigma_2 - sigma_L = (1/6) sum s_i s_j [- (1/30) s_x s_y s_z]
+// is formed directly, so nothing cancels near k = 0), integrated by the tensor
+// cube of a composite Gauss-Legendre rule whose panels halve towards k = 0
+// and are split into parts of at most 16 periods of cos(n_max k) (16, 32 or
+// 64 nodes a part by its number of periods).  The triple sum is three
+// contractions: over x nodes, y nodes, then z nodes, in chunks of z nodes.
+// ---------------------------------------------------------------------------
+constexpr int kMehrGrade = 22;  // the panel next to k = 0 is [0, pi 2^-22]
+
+static void mehr_rule(int n_max, std::vector<double>& k, std::vector<double>& w) {
+  std::vector<double> x16, w16, x32, w32, x64, w64;
+  gauss_legendre(16, x16, w16);
+  gauss_legendre(32, x32, w32);
+  gauss_legendre(64, x64, w64);
+  k.clear();
+  w.clear();
+  std::vector<double> edges{0.0};
+  for (int j = kMehrGrade; j >= 0; --j) edges.push_back(kPi * std::ldexp(1.0, -j));
+  for (size_t e = 0; e + 1 < edges.size(); ++e) {
+    const double a = edges[e], b = edges[e + 1];
+    const double periods = (b - a) * std::max(n_max, 1) / (2.0 * kPi);
+    const int parts = std::max(1, int(std::ceil(periods / 16.0)));
+    const double pp = periods / parts;
+    const std::vector<double>& gx = pp <= 1.5 ? x16 : pp <= 5.0 ? x32 : x64;
+    const std::vector<double>& gw = pp <= 1.5 ? w16 : pp <= 5.0 ? w32 : w64;
+    for (int p = 0; p < parts; ++p) {
+      const double c = a + (b - a) * p / parts, d = a + (b - a) * (p + 1) / parts;
+      const double half = 0.5 * (d - c), mid = 0.5 * (d + c);
+      for (size_t i = 0; i < gx.size(); ++i) {
+        k.push_back(mid + half * gx[i]);
+        w.push_back(half * gw[i]);
+      }
+    }
+  }
+}
+
+// T[n][a] = cos(n k_a) w_a, n < ext
+__global__ void k_mehr_cos(const double* __restrict__ k, const double* __restrict__ w, int K, int ext,
+                           double* __restrict__ T) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)ext * K) return;
+  const int n = int(idx / K), a = int(idx % K);
+  T[idx] = cos(double(n) * k[a]) * w[a];
+}
+
+// X[al][b][c] = (sigma_2 - sigma_L) / (sigma_L sigma_2) at (s_x, s_y, s_z) =
+// (s[c], s[b], s[a0 + al])
+__global__ void k_mehr_delta(const double* __restrict__ s, int K, int a0, int na, int order,
+                             double* __restrict__ X) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)na * K * K) return;
+  const int c = int(idx % K);
+  const int b = int((idx / K) % K);
+  const int al = int(idx / ((long long)K * K));
+  const double sx = s[c], sy = s[b], sz = s[a0 + al];
+  const double S = sx + sy + sz;
+  double dif = (sx * sy + sy * sz + sz * sx) / 6.0;  // sigma_2 - sigma_L
+  if (order == 6) dif -= sx * sy * sz / 30.0;
+  const double sl = S - dif;
+  X[idx] = dif / (sl * S);
+}
+
+// General strided double GEMM, 64 x 64 tiles:
+//   C[i * sCi + j] (=, or += when acc) alpha * sum_l A[i * sAi + l * sAl] * B[j * sBj + l * sBl]
+// over batch b (blockIdx.z) with offsets b * sAb, b * sBb, b * sCb.
+__global__ void __launch_bounds__(256)
+k_gemm_s(const double* __restrict__ A, long long sAb, long long sAi, long long sAl, const double* __restrict__ B,
+         long long sBb, long long sBj, long long sBl, double* __restrict__ C, long long sCb, long long sCi, int ni,
+         int nj, int nl, double alpha, int acc) {
+  __shared__ double as[GK][GT + 1];
+  __shared__ double bs[GK][GT + 1];
+  const int bt = blockIdx.z;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  const double* Ab = A + bt * sAb;
+  const double* Bb = B + bt * sBb;
+  double accv[4][4] = {};
+  for (int l0 = 0; l0 < nl; l0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      // the fast index of the load follows whichever of the operand's
+      // strides is 1 (coalesced rows of the tile)
+      int r, l;
+      if (sAl == 1) { r = e / GK; l = e % GK; } else { l = e / GT; r = e % GT; }
+      const int gi = i0 + r, gl = l0 + l;
+      as[l][r] = (gi < ni && gl < nl) ? Ab[gi * sAi + gl * sAl] : 0.0;
+      if (sBl == 1) { r = e / GK; l = e % GK; } else { l = e / GT; r = e % GT; }
+      const int gj = j0 + r, gl2 = l0 + l;
+      bs[l][r] = (gj < nj && gl2 < nl) ? Bb[gj * sBj + gl2 * sBl] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < GK; ++l) {
+      double xv[4], yv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[q] = as[l][ti + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yv[q] = bs[l][tj + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) accv[q][c] = fma(xv[q], yv[c], accv[q][c]);
+    }
+    __syncthreads();
+  }
+  double* Cb = C + bt * sCb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gi = i0 + ti + 16 * q;
+    if (gi >= ni) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gj = j0 + tj + 16 * c;
+      if (gj >= nj) continue;
+      double* o = Cb + gi * sCi + gj;
+      *o = acc ? *o + alpha * accv[q][c] : alpha * accv[q][c];
+    }
+  }
+}
+
+static hipError_t gemm_s(const double* A, long long sAb, long long sAi, long long sAl, const double* B, long long sBb,
+                         long long sBj, long long sBl, double* C, long long sCb, long long sCi, int ni, int nj, int nl,
+                         int batch, double alpha, bool acc, hipStream_t st) {
+  dim3 grid((nj + GT - 1) / GT, (ni + GT - 1) / GT, batch);
+  hipLaunchKernelGGL(k_gemm_s, grid, dim3(256), 0, st, A, sAb, sAi, sAl, B, sBb, sBj, sBl, C, sCb, sCi, ni, nj, nl,
+                     alpha, acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+// R applied to the even table G (octant of extents ez x ey x ex): K[n] =
+// sum_o coef_o G[|n + o|] on the octant kz x ky x kx.
+struct MehrStencil {
+  int n;
+  int o[33][3];  // offsets (x, y, z)
+  double c[33];
+};
+
+static MehrStencil mehr_rhs_stencil(int order) {
+  // R on a 5^3 grid: apply the difference operators to a unit impulse
+  double d[5][5][5] = {}, t1[5][5][5] = {}, t2[5][5][5] = {};
+  auto d2 = [](const double (&in)[5][5][5], double (&out)[5][5][5], int axis) {
+    for (int z = 0; z < 5; ++z)
+      for (int y = 0; y < 5; ++y)
+        for (int x = 0; x < 5; ++x) {
+          auto at = [&](int dz, int dy, int dx) {
+            const int zz = z + dz, yy = y + dy, xx = x + dx;
+            return (zz < 0 || zz > 4 || yy < 0 || yy > 4 || xx < 0 || xx > 4) ? 0.0 : in[zz][yy][xx];
+          };
+          const int e[3][3] = {{0, 0, 1}, {0, 1, 0}, {1, 0, 0}};  // x, y, z as (dz, dy, dx)
+          out[z][y][x] = at(e[axis][0], e[axis][1], e[axis][2]) - 2.0 * in[z][y][x] +
+                         at(-e[axis][0], -e[axis][1], -e[axis][2]);
+        }
+  };
+  double R[5][5][5] = {};
+  d[2][2][2] = 1.0;
+  R[2][2][2] = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    d2(d, t1, i);
+    for (int z = 0; z < 5; ++z)
+      for (int y = 0; y < 5; ++y)
+        for (int x = 0; x < 5; ++x) R[z][y][x] += t1[z][y][x] / 12.0;
+    if (order == 6) {
+      d2(t1, t2, i);  // d4 along i
+      for (int z = 0; z < 5; ++z)
+        for (int y = 0; y < 5; ++y)
+          for (int x = 0; x < 5; ++x) R[z][y][x] -= t2[z][y][x] / 240.0;
+      for (int j = i + 1; j < 3; ++j) {
+        d2(t1, t2, j);
+        for (int z = 0; z < 5; ++z)
+          for (int y = 0; y < 5; ++y)
+            for (int x = 0; x < 5; ++x) R[z][y][x] += t2[z][y][x] / 90.0;
+      }
+    }
+  }
+  MehrStencil m{};
+  for (int z = 0; z < 5; ++z)
+    for (int y = 0; y < 5; ++y)
+      for (int x = 0; x < 5; ++x)
+        if (R[z][y][x] != 0.0 && m.n < 33) {
+          m.o[m.n][0] = x - 2;
+          m.o[m.n][1] = y - 2;
+          m.o[m.n][2] = z - 2;
+          m.c[m.n] = R[z][y][x];
+          ++m.n;
+        }
+  return m;
+}
+
+__global__ void k_mehr_rhs(MehrStencil m, const double* __restrict__ G, int ez, int ey, int ex, int kz, int ky,
+                           int kx, double* __restrict__ K) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)kz * ky * kx) return;
+  const int x = int(idx % kx);
+  const int y = int((idx / kx) % ky);
+  const int z = int(idx / ((long long)kx * ky));
+  double v = 0.0;
+  for (int q = 0; q < m.n; ++q) {
+    const int xx = abs(x + m.o[q][0]), yy = abs(y + m.o[q][1]), zz = abs(z + m.o[q][2]);
+    v = fma(m.c[q], G[((long long)zz * ey + yy) * ex + xx], v);
+  }
+  K[idx] = v;
+}
+
+// G_L = -S + D on the extended octant (S = -G1 at off_G0, D at off_D)
+__global__ void k_mehr_sum(const double* __restrict__ S, long long n, double* __restrict__ D) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) D[idx] -= S[idx];
+}
+
+MehrScratch mehr_scratch_layout(int kz, int ky, int kx, int order) {
+  MehrScratch m{};
+  m.r = order == 6 ? 2 : 1;
+  m.ez = kz + m.r;
+  m.ey = ky + m.r;
+  m.ex = kx + m.r;
+  m.base = green_scratch_layout(m.ez, m.ey, m.ex);
+  std::vector<double> k, w;
+  mehr_rule(std::max(m.ez, std::max(m.ey, m.ex)) - 1, k, w);
+  m.K = int(k.size());
+  const long long KK = (long long)m.K * m.K;
+  m.chunk = int(std::max(1LL, std::min((long long)m.K, (32LL << 20) / KK)));
+  size_t off = m.base.bytes;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  m.off_k = take(sizeof(double) * m.K);
+  m.off_w = take(sizeof(double) * m.K);
+  m.off_s = take(sizeof(double) * m.K);
+  m.off_Tz = take(sizeof(double) * (size_t)m.ez * m.K);
+  m.off_Ty = take(sizeof(double) * (size_t)m.ey * m.K);
+  m.off_Tx = take(sizeof(double) * (size_t)m.ex * m.K);
+  m.off_X = take(sizeof(double) * (size_t)m.chunk * KK);
+  m.off_T1 = take(sizeof(double) * (size_t)m.chunk * m.K * m.ex);
+  m.off_T2 = take(sizeof(double) * (size_t)m.chunk * m.ey * m.ex);
+  m.off_D = take(sizeof(double) * (size_t)m.ez * m.ey * m.ex);
+  m.bytes = off;
+  return m;
+}
+
+template <typename T>
+hipError_t build_green_mehr_t(int order, int kz, int ky, int kx, int gz, double h, int mx, int my, int mz,
+                              void* ghat, void* scratch, hipStream_t st) {
+  const MehrScratch m = mehr_scratch_layout(kz, ky, kx, order);
+  char* base = static_cast<char*>(scratch);
+  auto P = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  std::vector<double> t, w, k, kw, sv, Cx, Cy, Cz;  // host data of the asynchronous copies
+  // G1 on the extended octant: S = -G1 at base.off_G0
+  GCHECK(lgf7_octant(m.ez, m.ey, m.ex, m.base, base, t, w, st));
+  // D by the graded tensor rule
+  mehr_rule(std::max(m.ez, std::max(m.ey, m.ex)) - 1, k, kw);
+  const int K = m.K;
+  sv.resize(K);
+  for (int a = 0; a < K; ++a) {
+    const double sn = std::sin(0.5 * k[a]);
+    sv[a] = 4.0 * sn * sn;
+  }
+  GCHECK(hipMemcpyAsync(P(m.off_k), k.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(m.off_w), kw.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(P(m.off_s), sv.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
+  const int ext[3] = {m.ez, m.ey, m.ex};
+  const size_t offT[3] = {m.off_Tz, m.off_Ty, m.off_Tx};
+  for (int i = 0; i < 3; ++i) {
+    const long long n = (long long)ext[i] * K;
+    hipLaunchKernelGGL(k_mehr_cos, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P(m.off_k), P(m.off_w), K,
+                       ext[i], P(offT[i]));
+    GCHECK(hipGetLastError());
+  }
+  const long long plane = (long long)m.ey * m.ex;
+  for (int a0 = 0; a0 < K; a0 += m.chunk) {
+    const int na = std::min(m.chunk, K - a0);
+    const long long n = (long long)na * K * K;
+    hipLaunchKernelGGL(k_mehr_delta, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P(m.off_s), K, a0, na,
+                       order, P(m.off_X));
+    GCHECK(hipGetLastError());
+    // T1[(a, b)][nx] = sum_c X[(a, b)][c] Tx[nx][c]
+    GCHECK(gemm_s(P(m.off_X), 0, K, 1, P(m.off_Tx), 0, K, 1, P(m.off_T1), 0, m.ex, na * K, m.ex, K, 1, 1.0,
+                  false, st));
+    // T2[a][ny][nx] = sum_b Ty[ny][b] T1[a][b][nx]
+    GCHECK(gemm_s(P(m.off_Ty), 0, K, 1, P(m.off_T1), (long long)K * m.ex, 1, m.ex, P(m.off_T2), plane, m.ex, m.ey,
+                  m.ex, K, na, 1.0, false, st));
+    // D[nz][(ny, nx)] += -(1/pi^3) sum_a Tz[nz][a0 + a] T2[a][(ny, nx)]
+    GCHECK(gemm_s(P(m.off_Tz) + a0, 0, K, 1, P(m.off_T2), 0, 1, plane, P(m.off_D), 0, plane, m.ez, int(plane), na,
+                  1, -1.0 / (kPi * kPi * kPi), a0 > 0, st));
+  }
+  // G_L = G1 + D (in place at off_D), then K = R G_L on the octant -> off_G0
+  {
+    const long long n = (long long)m.ez * plane;
+    hipLaunchKernelGGL(k_mehr_sum, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P(m.base.off_G0), n,
+                       P(m.off_D));
+    GCHECK(hipGetLastError());
+    const long long nk = (long long)kz * ky * kx;
+    hipLaunchKernelGGL(k_mehr_rhs, dim3(unsigned((nk + 255) / 256)), dim3(256), 0, st, mehr_rhs_stencil(order),
+                       P(m.off_D), m.ez, m.ey, m.ex, kz, ky, kx, P(m.base.off_G0));
+    GCHECK(hipGetLastError());
+  }
+  // G_hat = (h^2 / (mx my mz)) * DCT(K)
+  GCHECK(dct3_store<T>(kz, ky, kx, gz, (h * h) / (double(mx) * double(my) * double(mz)), m.base, base, Cx, Cy, Cz,
+                       ghat, st));
+  // the host vectors above must outlive the copies
+  return hipStreamSynchronize(st);
+}
+
 template <typename T>
 __global__ void k_twiddles(const double* __restrict__ src, int n, cx<T>* __restrict__ dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -598,11 +921,15 @@ hipError_t build_twiddles_t(int M, void* dst, void* scratch, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t build_green(bool f64, const int bc[3], int kz, int ky, int kx, int gz, double h, int mx, int my,
-                       int mz, void* ghat, void* scratch, hipStream_t st) {
+hipError_t build_green(bool f64, const int bc[3], int green, int kz, int ky, int kx, int gz, double h, int mx,
+                       int my, int mz, void* ghat, void* scratch, hipStream_t st) {
   const bool all_unb = !bc || (bc[0] == UPS_BC_UNB && bc[1] == UPS_BC_UNB && bc[2] == UPS_BC_UNB);
   hipError_t e;
-  if (all_unb)
+  if (green == UPS_GREEN_LGF4_MEHR || green == UPS_GREEN_LGF6_MEHR) {
+    const int order = green == UPS_GREEN_LGF4_MEHR ? 4 : 6;
+    e = f64 ? build_green_mehr_t<double>(order, kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
+            : build_green_mehr_t<float>(order, kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
+  } else if (all_unb)
     e = f64 ? build_green_t<double>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st)
             : build_green_t<float>(kz, ky, kx, gz, h, mx, my, mz, ghat, scratch, st);
   else

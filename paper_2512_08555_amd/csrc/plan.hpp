@@ -17,6 +17,7 @@ struct PlanGeom {
   int gz;                    // iz pitch of G_hat [iy][kx][iz] (elements)
   int ncomp;
   int bc[3];                 // ups_bc per axis (x, y, z); both sides equal
+  int green;                 // ups_green
   double h;
   long long plane, comp_w;   // W strides (complex elements)
   size_t solve_work;         // bytes of W

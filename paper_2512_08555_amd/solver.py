@@ -22,10 +22,14 @@ def _stream_handle(stream=None):
 BC_CODES = {"unb": capi.UPS_BC_UNB, "per": capi.UPS_BC_PER, "even": capi.UPS_BC_EVEN, "odd": capi.UPS_BC_ODD}
 
 
-def make_problem(shape, h, prec="f64", ncomp=1, pad=None, bc=None):
+GREEN_CODES = {"lgf2": capi.UPS_GREEN_LGF2, "mehr4": capi.UPS_GREEN_LGF4_MEHR, "mehr6": capi.UPS_GREEN_LGF6_MEHR}
+
+
+def make_problem(shape, h, prec="f64", ncomp=1, pad=None, bc=None, green="lgf2"):
     """ups_problem for a grid of shape (nz, ny, nx) with isotropic spacing h;
     bc: None (unbounded everywhere) or one of "unb", "per", "even", "odd"
-    per axis in (z, y, x) order, the same on both sides of the axis."""
+    per axis in (z, y, x) order, the same on both sides of the axis; green:
+    "lgf2" (7-point operator), "mehr4" or "mehr6" (the Mehrstellen pairs)."""
     nz, ny, nx = (int(v) for v in shape)
     p = capi.ups_problem()
     capi.lib().ups_problem_init(C.byref(p))
@@ -37,6 +41,7 @@ def make_problem(shape, h, prec="f64", ncomp=1, pad=None, bc=None):
     if pad is not None:
         mz, my, mx = (int(v) for v in pad)
         p.pad[0], p.pad[1], p.pad[2] = mx, my, mz
+    p.green = GREEN_CODES[green] if isinstance(green, str) else int(green)
     if bc is not None:
         codes = [BC_CODES[b] if isinstance(b, str) else int(b) for b in bc]
         for axis, code in zip((2, 1, 0), codes):   # (z, y, x) -> ABI axis index
@@ -51,7 +56,7 @@ class Plan:
     by the constructor unless setup=False) allocates the green and work
     buffers with torch on the current device and builds G_hat."""
 
-    def __init__(self, shape, h, prec="f64", ncomp=1, pad=None, setup=True, problem=None, bc=None):
+    def __init__(self, shape, h, prec="f64", ncomp=1, pad=None, setup=True, problem=None, bc=None, green="lgf2"):
         self.shape = tuple(int(v) for v in shape)
         self.h = float(h)
         self.prec = prec
@@ -59,7 +64,7 @@ class Plan:
         self.bc = tuple(bc) if bc is not None else ("unb",) * 3
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         L = capi.lib()
-        self._prob = problem if problem is not None else make_problem(self.shape, h, prec, ncomp, pad, bc)
+        self._prob = problem if problem is not None else make_problem(self.shape, h, prec, ncomp, pad, bc, green)
         handle = C.c_void_p()
         capi.check(L.ups_plan_create(C.byref(self._prob), C.byref(handle)))
         self._h = handle

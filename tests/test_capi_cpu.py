@@ -107,9 +107,11 @@ def test_validation_errors():
     p.green = capi.UPS_GREEN_LGF4_MEHR
     assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
 
-    p = make_problem((32, 32, 32), 1 / 32)
-    p.green = capi.UPS_GREEN_LGF4_MEHR
-    assert _create(p)[0] == capi.UPS_ERR_UNSUPPORTED
+    for g in ("mehr4", "mehr6"):
+        p = make_problem((32, 32, 32), 1 / 32, green=g)
+        s, h, _ = _create(p)
+        assert s == capi.UPS_OK
+        L.ups_plan_destroy(h)
 
     p = make_problem((32, 32, 32), 1 / 32, ncomp=9)
     assert _create(p)[0] == capi.UPS_ERR_INVALID_ARG

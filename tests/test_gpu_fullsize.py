@@ -142,3 +142,66 @@ def test_ragged_z_f64_at_1024_rows_past_2_32_bytes():
     err = _rel_inf(u, ref)
     print("ragged z f64 rel Linf %.3e" % err, flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_mehrstellen_kernel_513_octant(order):
+    """The 512^3 Mehrstellen kernel K = R G_L, recovered from the FP64
+    G_hat octant by the inverse DCT-I: equal to the oracle's table near the
+    origin, L K = R delta over the whole octant (L and R commute), and the
+    free-space decay K ~ -1/(4 pi r) + O(r^-3) out to r = 512."""
+    import scipy.fft as sfft
+    from oracle import mehrstellen as oms
+    from paper_2512_08555_amd.solver import Plan
+    _announce("mehrstellen %d kernel 513^3 octant f64" % order)
+    n = 512
+    h = 1.0 / n
+    plan = Plan((n, n, n), h, "f64", green="mehr%d" % order)
+    G = plan.ghat().cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    K = sfft.idctn(G * ((2 * n) ** 3 / (h * h)), type=1)
+    del G
+    ref = oms.kernel_table(12, 12, 12, order)
+    kmax = np.abs(ref).max()
+    err = np.abs(K[:12, :12, :12] - ref).max() / kmax
+    print("K near origin vs oracle: rel %.3e" % err, flush=True)
+    assert err < 1e-12
+    # L K = R delta on the octant (mirror layer at index -1)
+    Kp = np.pad(K, ((1, 0), (1, 0), (1, 0)), mode="reflect")
+    LK = oms.apply_stencil(Kp, "L", order)
+    del Kp
+    d = np.zeros((9, 9, 9))
+    d[4, 4, 4] = 1.0
+    Rd = oms.apply_stencil(d, "R", order)           # R delta (radius <= 2), centred
+    rr = Rd.shape[0] // 2
+    LK[:rr + 1, :rr + 1, :rr + 1] -= Rd[rr:, rr:, rr:]
+    res = np.abs(LK).max() / kmax
+    del LK
+    print("L K - R delta: rel %.3e" % res, flush=True)
+    assert res < 1e-11
+    for p in [(511, 0, 0), (300, 300, 0), (290, 290, 290), (400, 100, 7)]:
+        r = float(np.sqrt(sum(v * v for v in p)))
+        dev = (K[p[2], p[1], p[0]] + 1.0 / (4 * np.pi * r)) * r ** 3
+        print("r %.0f: (K + 1/(4 pi r)) r^3 = %.4e" % (r, dev), flush=True)
+        assert abs(dev) < 0.05
+
+
+def test_mehrstellen_512_f64_solve_satisfies_its_equation():
+    """The 512^3 FP64 solve with the sixth-order pair: (1/h^2) L6 u = R6 f
+    at every interior cell (the source vanishes outside the box)."""
+    from oracle import mehrstellen as oms
+    from paper_2512_08555_amd.solver import Plan
+    cfg = workloads.config_c3()
+    _announce("mehrstellen 6 512^3 f64 solve residual")
+    f, h = cfg["f"], cfg["h"]
+    plan = Plan(cfg["shape"], h, "f64", green="mehr6")
+    u = plan.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    del plan
+    torch.cuda.empty_cache()
+    Lu = oms.apply_stencil(u, "L", 6) / (h * h)
+    del u
+    Rf = oms.apply_stencil(np.pad(f, 2), "R", 6)[1:-1, 1:-1, 1:-1]
+    res = np.abs(Lu - Rf).max() / np.abs(Rf).max()
+    print("L6 u / h^2 - R6 f: rel %.3e" % res, flush=True)
+    assert res < 1e-8
