@@ -26,6 +26,10 @@ multiresolution grids"):
                   mehrstellen_discr4/6): the LGF of L by the 7-point LGF plus
                   a graded quadrature of the bounded difference of the inverse
                   symbols, the kernel R G_L, and the solve with it.
+* ``multigrid`` -- the V(eta1, eta2) full-approximation cycle around the
+                  unbounded solve (Sec. 3.1, Alg. amg_vcycle) on a hierarchy
+                  of nested refined boxes, and the composite equations its
+                  fixed point satisfies, solved directly for small grids.
 * ``analytic`` -- closed forms used as pins: Watson's constant, the Gaussian
                   charge potential, the paper's compact manufactured solution
                   (Sec. 4.2, unbounded domains).
@@ -38,12 +42,12 @@ from .lgf import (watson_g0, lgf_table, lgf_point_adaptive, lgf_far_field,
 from .spectrum import green_spectrum_raw, green_spectrum_rfft, green_spectrum_scaled
 from .solve import (solve, solve_full, brute_force, brute_force_adjoint,
                     adjoint, laplacian7_interior)
-from . import analytic, bc, mehrstellen
+from . import analytic, bc, mehrstellen, multigrid
 
 __all__ = [
     "watson_g0", "lgf_table", "lgf_point_adaptive", "lgf_far_field", "lgf_tail",
     "quadrature_nodes", "hankel_coefficients",
     "green_spectrum_raw", "green_spectrum_rfft", "green_spectrum_scaled",
     "solve", "solve_full", "brute_force", "brute_force_adjoint", "adjoint",
-    "laplacian7_interior", "analytic", "bc", "mehrstellen",
+    "laplacian7_interior", "analytic", "bc", "mehrstellen", "multigrid",
 ]
