@@ -255,6 +255,53 @@ def calibrate_copy(nbytes=2 << 30, reps=3):
     return {"bytes": nbytes, "reps": reps, "grid_elements": a.numel()}
 
 
+def mg_leg(n=512, prec="f32", reps=5):
+    """The multigrid V(2, 2) cycle (Sec. 3.1) around the solve: level 0 the
+    n^3 grid solved by the FFT plan, level 1 a (n + 1)^3 box over the
+    central half at spacing h / 2, each level with its own seeded
+    blob-plus-noise source (a timing workload: the values do not change the
+    work).
+    ms per cycle (HIP events on the caller's stream), and the composite
+    residual's reduction per cycle from zero."""
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.solver import Multigrid, Plan
+    h0 = 1.0 / n
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = Plan((n, n, n), h0, prec)
+    mg = Multigrid(plan, [((n // 4,) * 3, (n // 2,) * 3)])
+    f0 = torch.from_numpy(workloads.config_blobs_noise(n, 2)).to("cuda", dt)
+    f1 = torch.from_numpy(workloads.config_blobs_noise(n + 1, 3)).to("cuda", dt) * 0.25
+    fs = [f0, f1]
+    us = mg.zeros()
+    res = [max(mg.residuals(fs, us))]
+    for _ in range(3):
+        mg.cycle(fs, us, 2, 2)
+        res.append(max(mg.residuals(fs, us)))
+    stream = torch.cuda.current_stream()
+    out = {"levels": [list(s) for s in mg.shapes], "precision": prec,
+           "residual_per_cycle": [float(r) for r in res],
+           "rate": float((res[-1] / res[1]) ** 0.5) if res[1] > 0 else None}
+    for nu in ((2, 2), (1, 1)):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            mg.cycle(fs, us, *nu)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["ms_per_cycle_V%d%d" % nu] = e0.elapsed_time(e1) / reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    u0 = torch.empty_like(f0)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.solve(f0, out=u0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["level0_solve_ms"] = e0.elapsed_time(e1) / reps
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +312,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-mg", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB copy kernel (for counter calibration runs)")
     args = ap.parse_args()
@@ -356,6 +404,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_grad:
         extra["grad_256"] = grad_leg()
+        torch.cuda.empty_cache()
+    if not args.no_mg:
+        extra["multigrid"] = mg_leg(n)
         torch.cuda.empty_cache()
     if args.calibrate_copy:
         extra["copy_calibration"] = calibrate_copy()

@@ -361,6 +361,77 @@ int ups_batch_launches(ups_batch_t batch, int pass);
 
 ups_status ups_batch_destroy(ups_batch_t batch);
 
+/* ---- multigrid cycle around the solve ---------------------------------------
+ * The V(nu1, nu2) full-approximation cycle of Sec. 3.1 (Alg. amg_vcycle) on
+ * a hierarchy of nested refined boxes, with an unbounded (or mixed) solve
+ * of the plan as the direct solver on the coarsest level.  All levels hold
+ * nodes, arrays laid out as the plan's ([z][y][x], x fastest, the plan's
+ * precision):
+ *   - level 0 is the plan's grid (nx, ny, nz points, spacing h);
+ *   - level k >= 1 refines level k-1 by 2: a box of 2 cells[k-1][a] + 1
+ *     nodes along axis a at spacing h / 2^k, whose node 2 i lies on node
+ *     origin[k-1][a] + i of level k-1.  Its outer layer of nodes is ghost
+ *     data, reconstructed from level k-1 by 4-point cubic interpolation
+ *     ((-1, 9, 9, -1)/16 at each odd fine index, one axis at a time); the
+ *     nodes inside are its unknowns.  Each box lies strictly inside its parent's unknowns:
+ *     cells >= 2, origin >= 1 and origin + cells <= n_parent - 2.
+ * One cycle, for k = l .. 1: ghosts of u_k from u_{k-1}, nu1 red-black
+ * Gauss-Seidel iterations (red = even index sum in the box frame, first),
+ * r_k = f_k - Lap u_k with the 7-point stencil of eq. cross_discr2; on the
+ * parent's unknowns inside the box's footprint u_{k-1} = injection of u_k,
+ * f_{k-1} = full weighting ((1/4)[1 2 1] per axis) of r_k + Lap u_{k-1};
+ * u_{k-1} on the whole footprint is stored.  Level 0 is solved by the plan.
+ * For k = 1 .. l: u_k += trilinear prolongation of (new minus stored
+ * u_{k-1}) on the unknowns, ghosts reconstructed from u_{k-1}, nu2
+ * Gauss-Seidel iterations.  The coarse kernel must be the LGF of the 7-point
+ * operator (Sec. 3.3): plans with the Mehrstellen kernels are refused.  The
+ * caller's sources are read only; the modified sources of levels 0 .. l-1
+ * live in the work buffer. */
+#define UPS_MG_MAX_LEVELS 8
+
+typedef struct ups_mg_s* ups_mg_t;
+
+typedef struct {
+  int levels;                        /* refined levels l, 0 .. UPS_MG_MAX_LEVELS */
+  int origin[UPS_MG_MAX_LEVELS][3];  /* box k+1: its node 0 in level-k nodes (x, y, z) */
+  int cells[UPS_MG_MAX_LEVELS][3];   /* box k+1: its extent in level-k cells (x, y, z) */
+} ups_mg_hierarchy;
+
+/* Validate the hierarchy against the plan (host only; the plan need not be
+ * set up yet, but must outlive the cycle object).  Errors: INVALID_ARG (null
+ * argument, a box outside its parent's unknowns, fewer than 2 cells, more
+ * than 2^31 - 1 nodes on a level), UNSUPPORTED (a plan with several
+ * components or a Mehrstellen kernel, levels above UPS_MG_MAX_LEVELS). */
+ups_status ups_mg_create(ups_plan_t coarse, const ups_mg_hierarchy* hier, ups_mg_t* out);
+
+/* Node counts (x, y, z) of level 0 .. l. */
+ups_status ups_mg_level_shape(ups_mg_t mg, int level, int n[3]);
+
+/* Bytes of the work buffer: the modified sources of levels 0 .. l-1, one
+ * residual array of the largest refined level, the stored footprints and
+ * the residual norms. */
+ups_status ups_mg_sizes(ups_mg_t mg, size_t* work_bytes);
+
+/* Bind the caller's work buffer (256-byte aligned, at least ups_mg_sizes
+ * bytes; the caller owns it).  Errors: INVALID_ARG, WORKSPACE. */
+ups_status ups_mg_setup(ups_mg_t mg, void* work, size_t work_bytes);
+
+/* One V(nu1, nu2) cycle on `stream`: f[k] (read only) and u[k] (updated in
+ * place, ghost layers included) are device arrays of level k, k = 0 .. l.
+ * Uses the plan's work buffer and side stream (one cycle or solve in flight
+ * per plan).  Errors: INVALID_ARG (null or misaligned arrays, nu1 or nu2
+ * outside 0 .. 64), STATE (no work buffer bound, plan not set up), DEVICE. */
+ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int nu1, int nu2, void* stream);
+
+/* Composite residual norms: norms[k] = max |f_k - Lap u_k| over the
+ * unknowns of level k outside the interior of box k+1's footprint (level 0:
+ * its nodes with all six neighbours in the grid), after the ghosts of
+ * levels 1 .. l are refreshed from their parents (u is written there).
+ * Waits for `stream`.  Errors as ups_mg_cycle. */
+ups_status ups_mg_residual(ups_mg_t mg, const void* const* f, void* const* u, double* norms, void* stream);
+
+ups_status ups_mg_destroy(ups_mg_t mg);
+
 #ifdef __cplusplus
 }
 #endif

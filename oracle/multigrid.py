@@ -9,8 +9,8 @@ nodes at spacing h_k = h0 / 2^k that refines a part of level k - 1.  Patch k
 is given by its origin c_k (a node of level k - 1, per axis z, y, x) and its
 extent m_k in cells of level k - 1, so it holds 2 m_k + 1 nodes per axis and
 its node 2 i lies on node c_k + i of its parent.  Its outer layer of nodes
-is ghost data, reconstructed from the parent by the trilinear prolongation;
-the nodes inside are its unknowns.  The patch lies strictly inside the
+is ghost data, reconstructed from the parent; the nodes inside are its
+unknowns.  The patch lies strictly inside the
 parent's unknowns: 1 <= c_k and c_k + m_k <= n_{k-1} - 2 (for level 0 every
 node is an unknown of the direct solve, the same bound keeps the stencils
 of the footprint inside the grid).  Arrays are indexed [z, y, x].
@@ -23,7 +23,15 @@ Operators (Sec. 3.1):
 * residual r = f - Lap u on the unknowns;
 * restriction of r: full weighting, the tensor product of (1/4)[1 2 1];
 * restriction of u: injection;
-* prolongation (of the correction and of the ghost layer): trilinear.
+* prolongation of the correction: trilinear;
+* ghost reconstruction at the resolution jump: the paper keeps it apart from
+  the prolongation and describes it as a (higher-order) polynomial
+  interpolation; it is read here as the 4-point cubic interpolation
+  (-1, 9, 9, -1)/16 at every odd fine index, one axis at a time, from the
+  parent's values on the footprint extended by one node on every side.
+  (Trilinear ghost values leave an O(1) truncation error on the layer next
+  to the jump and make the composite solution first order; the cubic ones
+  keep it second order.)
 
 One cycle (full-approximation scheme), for k = l .. 1: fill the ghosts of u_k
 from u_{k-1}, eta1 smoothing steps, r_k = f_k - Lap u_k, then on the
@@ -34,15 +42,16 @@ footprint (c_k .. c_k + m_k) as u_hat_{k-1}.  Level 0 is then solved directly
 with the unbounded FFT convolution (any kernel callable may stand in).
 For k = 1 .. l: the correction e = u_{k-1} - u_hat_{k-1} (new minus stored;
 the algorithm prints the difference the other way round, which would move
-u_k away from the coarse solution), u_k += prolongation of e on the
-unknowns, ghosts from u_{k-1}, eta2 smoothing steps.  The sources f_k the
+u_k away from the coarse solution), u_k += trilinear prolongation of e on
+the unknowns, ghosts from u_{k-1}, eta2 smoothing steps.  The sources f_k the
 caller gives are not modified: each cycle works on copies, whose values in
 a child's footprint are replaced by the restriction.
 
 The converged composite solution satisfies, at every level, the 7-point
 equation at each unknown outside the interior of the child's footprint,
-injection consistency inside it, and ghost layers equal to the prolongation
-of the parent; ``composite_dense`` solves that system directly for pins.
+injection consistency inside it, and ghost layers equal to the cubic
+reconstruction from the parent; ``composite_dense`` solves that system
+directly for pins.
 """
 
 import numpy as np
@@ -166,10 +175,43 @@ def correction(u_coarse, u_hat):
     return u_coarse - u_hat
 
 
+def interp_cubic(E):
+    """From (m + 3) parent nodes per axis (the footprint and one node beyond
+    it on each side) to the 2 m + 1 fine nodes of the footprint: even fine
+    nodes take the parent value, odd ones (-1, 9, 9, -1)/16 of the four
+    nearest parent values; axis by axis, z, then y, then x."""
+    out = np.asarray(E, dtype=np.float64)
+    for a in range(3):
+        n = out.shape[a]
+        m = n - 3
+
+        def sl(lo, hi):
+            s = [slice(None)] * 3
+            s[a] = slice(lo, hi)
+            return tuple(s)
+        core = out[sl(1, n - 1)]
+        mid = (-out[sl(0, m)] + 9.0 * out[sl(1, m + 1)] + 9.0 * out[sl(2, m + 2)] - out[sl(3, m + 3)]) / 16.0
+        shp = list(core.shape)
+        shp[a] = 2 * m + 1
+        fine = np.zeros(shp)
+        ev = [slice(None)] * 3
+        ev[a] = slice(0, None, 2)
+        od = [slice(None)] * 3
+        od[a] = slice(1, None, 2)
+        fine[tuple(ev)] = core
+        fine[tuple(od)] = mid
+        out = fine
+    return out
+
+
+def _fp_ext(c, m):
+    """The footprint extended by one parent node on every side."""
+    return tuple(slice(int(ci) - 1, int(ci) + int(mi) + 2) for ci, mi in zip(c, m))
+
+
 def fill_ghosts(u_fine, u_parent, c, m):
-    """Ghost layer of a patch = trilinear prolongation of its parent's values
-    on the footprint."""
-    p = prolong(u_parent[_fp(c, m, False)])
+    """Ghost layer of a patch = cubic reconstruction from its parent."""
+    p = interp_cubic(u_parent[_fp_ext(c, m)])
     for a in range(3):
         for side in (0, -1):
             s = [slice(None)] * 3
@@ -254,7 +296,7 @@ def composite_dense(fs, patch, h0):
             free on it;
       u_0 = u_1 (injection) on the footprint interior;
       Lap u_1 = f_1 at the unknowns of level 1, whose ghost layer is the
-            trilinear prolongation of u_0 on the footprint.
+            cubic reconstruction from u_0.
 
     Returns (u_0, u_1)."""
     f0 = np.asarray(fs[0], dtype=np.float64)
@@ -289,13 +331,13 @@ def composite_dense(fs, patch, h0):
     for j, q in enumerate(fp_idx):
         A[N0 + j, q] = 1.0
         A[N0 + j, N0 + nF + inj[j]] = -1.0
-    # rows N0+nF ..: Lap u_1 = f_1; ghost values are linear in u_0 (prolongation)
-    full = np.arange(N0).reshape(n0)[_fp(c, m, False)]
+    # rows N0+nF ..: Lap u_1 = f_1; ghost values are linear in u_0
+    full = np.arange(N0).reshape(n0)[_fp_ext(c, m)]
     Pmat = np.zeros(tuple(n1) + (full.size,))
     for t in range(full.size):
         e = np.zeros(full.size)
         e[t] = 1.0
-        Pmat[..., t] = prolong(e.reshape(full.shape))
+        Pmat[..., t] = interp_cubic(e.reshape(full.shape))
     col_of = full.ravel()
     row0 = N0 + nF
     inv_h2 = 1.0 / (h1 * h1)

@@ -23,6 +23,7 @@ UPS_GREEN_LGF2, UPS_GREEN_LGF4_MEHR, UPS_GREEN_LGF6_MEHR = 0, 1, 2
 UPS_F64, UPS_F32 = 0, 1
 UPS_CELL, UPS_NODE = 0, 1
 UPS_NOALLOC_MAX_WORK = 64 << 20
+UPS_MG_MAX_LEVELS = 8
 
 
 class ups_problem(C.Structure):
@@ -35,6 +36,14 @@ class ups_problem(C.Structure):
         ("center", C.c_int),
         ("ncomp", C.c_int),
         ("pad", C.c_int * 3),
+    ]
+
+
+class ups_mg_hierarchy(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int),
+        ("origin", (C.c_int * 3) * UPS_MG_MAX_LEVELS),
+        ("cells", (C.c_int * 3) * UPS_MG_MAX_LEVELS),
     ]
 
 
@@ -78,6 +87,15 @@ SIGNATURES = {
     "ups_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
     "ups_batch_launches": (C.c_int, [C.c_void_p, C.c_int]),
     "ups_batch_destroy": (C.c_int, [C.c_void_p]),
+    "ups_mg_create": (C.c_int, [C.c_void_p, C.POINTER(ups_mg_hierarchy), C.POINTER(C.c_void_p)]),
+    "ups_mg_level_shape": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "ups_mg_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ups_mg_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ups_mg_cycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_int,
+                               C.c_void_p]),
+    "ups_mg_residual": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_double), C.c_void_p]),
+    "ups_mg_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None

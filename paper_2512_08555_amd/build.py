@@ -29,9 +29,9 @@ OUT_SAN = os.path.join(PKG, "libups_san.so")
 OBJ = os.path.join(PKG, "_build")
 OBJ_SAN = os.path.join(OBJ, "san")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["passes_f32.hip", "passes_f32m.hip", "passes_f64.hip", "passes.cpp", "green.hip", "debug.hip", "capi.cpp",
-           "batch.cpp", "autotune.cpp"]
-HOST_SOURCES = ["capi.cpp", "batch.cpp", "autotune.cpp"]
+SOURCES = ["passes_f32.hip", "passes_f32m.hip", "passes_f64.hip", "passes.cpp", "green.hip", "debug.hip",
+           "multigrid.hip", "capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp"]
+HOST_SOURCES = ["capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

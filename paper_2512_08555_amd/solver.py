@@ -345,3 +345,85 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Multigrid:
+    """The V(nu1, nu2) cycle of ups_mg_* around a set-up Plan (level 0).
+
+    patches: [(origin, cells), ...] for levels 1 .. l, each (z, y, x): box k
+    starts at node `origin` of level k-1 and spans `cells` cells of it
+    (2 cells + 1 nodes per axis).  Level arrays are torch tensors of the
+    plan's dtype, shapes `self.shapes`."""
+
+    def __init__(self, plan, patches, setup=True):
+        if plan.ncomp != 1:
+            raise ValueError("the coarse plan must have one component")
+        self.plan = plan
+        self.patches = [(tuple(int(v) for v in c), tuple(int(v) for v in m)) for c, m in patches]
+        hier = capi.ups_mg_hierarchy()
+        hier.levels = len(self.patches)
+        for k, (c, m) in enumerate(self.patches):
+            for a in range(3):                   # (z, y, x) -> ABI (x, y, z)
+                hier.origin[k][a] = c[2 - a]
+                hier.cells[k][a] = m[2 - a]
+        L = capi.lib()
+        handle = C.c_void_p()
+        capi.check(L.ups_mg_create(plan._h, C.byref(hier), C.byref(handle)))
+        self._h = handle
+        self.shapes = []
+        for k in range(len(self.patches) + 1):
+            n = (C.c_int * 3)()
+            capi.check(L.ups_mg_level_shape(self._h, k, n))
+            self.shapes.append((n[2], n[1], n[0]))
+        wb = C.c_size_t()
+        capi.check(L.ups_mg_sizes(self._h, C.byref(wb)))
+        self.work_bytes = wb.value
+        self.work = None
+        if setup:
+            self.setup()
+
+    @property
+    def levels(self):
+        return len(self.patches)
+
+    def setup(self, device=None):
+        dev = self.plan.work.device if device is None else torch.device(device)
+        self.work = torch.empty(max(self.work_bytes, 256), dtype=torch.uint8, device=dev)
+        capi.check(capi.lib().ups_mg_setup(self._h, C.c_void_p(self.work.data_ptr()), self.work_bytes))
+        return self
+
+    def zeros(self):
+        return [torch.zeros(s, dtype=self.plan.dtype, device=self.work.device) for s in self.shapes]
+
+    def _ptrs(self, arrs, name):
+        if len(arrs) != len(self.shapes):
+            raise ValueError("expected %d level arrays for %s" % (len(self.shapes), name))
+        for t, s in zip(arrs, self.shapes):
+            if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.plan.dtype
+                    or tuple(t.shape) != s or not t.is_contiguous()):
+                raise ValueError("%s: contiguous %s tensors of shapes %s" % (name, self.plan.dtype, self.shapes))
+        return (C.c_void_p * len(arrs))(*[t.data_ptr() for t in arrs])
+
+    def cycle(self, fs, us, nu1=2, nu2=2, stream=None):
+        """One V(nu1, nu2) cycle; us updated in place."""
+        capi.check(capi.lib().ups_mg_cycle(self._h, self._ptrs(fs, "f"), self._ptrs(us, "u"), int(nu1), int(nu2),
+                                           _stream_handle(stream)))
+        return us
+
+    def residuals(self, fs, us, stream=None):
+        """Composite residual norms of levels 0 .. l (waits; refreshes ghosts)."""
+        out = (C.c_double * len(self.shapes))()
+        capi.check(capi.lib().ups_mg_residual(self._h, self._ptrs(fs, "f"), self._ptrs(us, "u"), out,
+                                              _stream_handle(stream)))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().ups_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

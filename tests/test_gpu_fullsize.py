@@ -205,3 +205,30 @@ def test_mehrstellen_512_f64_solve_satisfies_its_equation():
     res = np.abs(Lu - Rf).max() / np.abs(Rf).max()
     print("L6 u / h^2 - R6 f: rel %.3e" % res, flush=True)
     assert res < 1e-8
+
+
+def test_multigrid_cycle_at_256_with_a_257_box_f64():
+    # one V(1, 1) cycle (Sec. 3.1) on the benchmark-size hierarchy: level 0 is
+    # the 256^3 FP64 solve, level 1 a 257^3 box over the central half; the
+    # whole of both levels against the oracle's cycle from the same start
+    from oracle import multigrid as omg
+    from paper_2512_08555_amd.solver import Multigrid
+    n = 256
+    h0 = 1.0 / n
+    patches = [((64, 64, 64), (128, 128, 128))]
+    _announce("multigrid 256^3 + 257^3 box f64, one V(1,1) cycle")
+    f0 = workloads.config_blobs_noise(n, 7)
+    rng = np.random.default_rng(8)
+    f1 = rng.standard_normal((2 * 128 + 1,) * 3)
+    plan = _plan((n, n, n), h0, "f64")
+    mg = Multigrid(plan, patches)
+    fd = [torch.from_numpy(f0).cuda(), torch.from_numpy(f1).cuda()]
+    ud = mg.zeros()
+    mg.cycle(fd, ud, 1, 1)
+    us = [np.zeros(s) for s in mg.shapes]
+    t0 = time.time()
+    omg.vcycle(us, [f0, f1], patches, h0, 1, 1)
+    print("oracle cycle: %.1f s" % (time.time() - t0), flush=True)
+    errs = [_rel_inf(a.cpu().numpy(), b) for a, b in zip(ud, us)]
+    print("multigrid 256 rel Linf per level %s" % errs, flush=True)
+    assert max(errs) < 1e-12

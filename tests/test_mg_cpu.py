@@ -1,0 +1,227 @@
+"""The multigrid cycle's C ABI on the host (no GPU): hierarchy validation,
+work-buffer sizes, state errors, and a host mirror of every kernel's launch
+geometry and index formulas (multigrid.hip) showing that each thread's
+accesses stay inside its arrays and that each kernel covers exactly the
+nodes it must."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2512_08555_amd import _capi as capi
+from paper_2512_08555_amd.lengths import auto_pad
+from paper_2512_08555_amd.solver import Multigrid, Plan
+
+BX, BY = 64, 4
+
+
+def _plan(shape=(20, 18, 22), prec="f64", **kw):
+    return Plan(shape, 0.05, prec, setup=False, pad=auto_pad(shape, prec), **kw)
+
+
+def test_shapes_and_sizes():
+    p = _plan()
+    mg = Multigrid(p, [((3, 2, 4), (6, 5, 7)), ((2, 3, 2), (4, 3, 5))], setup=False)
+    assert mg.shapes == [(20, 18, 22), (13, 11, 15), (9, 7, 11)]
+    el = 8
+    r256 = lambda v: (v + 255) // 256 * 256
+    want = r256(8 * 9)
+    want = r256(want + 20 * 18 * 22 * el)
+    want = r256(want + 13 * 11 * 15 * el)
+    want = r256(want + 13 * 11 * 15 * el)              # one residual array, the largest refined level
+    want = r256(want + 7 * 6 * 8 * el)
+    want = r256(want + 5 * 4 * 6 * el)
+    assert mg.work_bytes == want
+    assert Multigrid(_plan(prec="f32"), [], setup=False).work_bytes == 256
+
+
+@pytest.mark.parametrize("patch", [((0, 2, 2), (4, 4, 4)), ((2, 2, 2), (17, 4, 4)), ((2, 2, 2), (1, 4, 4)),
+                                   ((2, 2, 19), (4, 4, 2))])
+def test_box_outside_its_parent_is_rejected(patch):
+    with pytest.raises(capi.UpsError) as ei:
+        Multigrid(_plan(), [patch], setup=False)
+    assert ei.value.status == capi.UPS_ERR_INVALID_ARG
+
+
+def test_unsupported_coarse_plans():
+    with pytest.raises(capi.UpsError) as ei:
+        Multigrid(_plan(green="mehr4"), [((2, 2, 2), (4, 4, 4))], setup=False)
+    assert ei.value.status == capi.UPS_ERR_UNSUPPORTED and "7-point" in str(ei.value)
+    p3 = _plan(ncomp=3)
+    hier = capi.ups_mg_hierarchy()
+    h = C.c_void_p()
+    assert capi.lib().ups_mg_create(p3._h, C.byref(hier), C.byref(h)) == capi.UPS_ERR_UNSUPPORTED
+    hier.levels = capi.UPS_MG_MAX_LEVELS + 1
+    assert capi.lib().ups_mg_create(_plan()._h, C.byref(hier), C.byref(h)) == capi.UPS_ERR_UNSUPPORTED
+    assert capi.lib().ups_mg_create(None, C.byref(hier), C.byref(h)) == capi.UPS_ERR_INVALID_ARG
+
+
+def test_cycle_before_setup_is_a_state_error():
+    mg = Multigrid(_plan(), [((2, 2, 2), (4, 4, 4))], setup=False)
+    arr = (C.c_void_p * 2)(16, 16)
+    st = capi.lib().ups_mg_cycle(mg._h, arr, arr, 2, 2, None)
+    assert st == capi.UPS_ERR_STATE
+    wb = C.c_void_p(256)
+    assert capi.lib().ups_mg_setup(mg._h, wb, 0) == capi.UPS_ERR_WORKSPACE
+    assert capi.lib().ups_mg_setup(mg._h, C.c_void_p(8), mg.work_bytes) == capi.UPS_ERR_INVALID_ARG
+
+
+# --- host mirror of the kernels' launch geometry and index formulas ----------------------------
+
+def _threads(grid, block):
+    """All (blockIdx, threadIdx) of a launch as flat arrays per component."""
+    gx, gy, gz = grid
+    bx, by = block
+    B = np.stack(np.meshgrid(np.arange(gz), np.arange(gy), np.arange(gx), indexing="ij"), -1).reshape(-1, 3)
+    T = np.stack(np.meshgrid(np.arange(by), np.arange(bx), indexing="ij"), -1).reshape(-1, 2)
+    bz_, by_, bx_ = [np.repeat(B[:, i], len(T)) for i in range(3)]
+    ty, tx = [np.tile(T[:, i], len(B)) for i in range(2)]
+    return bx_, by_, bz_, tx, ty
+
+
+def _grid(nx, ny, nz):
+    return ((nx + BX - 1) // BX, (ny + BY - 1) // BY, nz)
+
+
+HIERARCHIES = [((12, 11, 13), [((3, 2, 4), (4, 5, 4))]),
+               ((13, 12, 14), [((3, 3, 3), (6, 5, 7)), ((2, 2, 3), (6, 6, 5))]),
+               ((9, 9, 9), [((1, 1, 1), (6, 6, 6))]),
+               ((70, 5, 67), [((1, 1, 30), (66, 2, 35))])]
+
+
+def _levels(n0, patches):
+    shapes = [n0]
+    for c, m in patches:
+        shapes.append(tuple(2 * v + 1 for v in m))
+    return shapes
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES)
+def test_smoothing_covers_each_unknown_of_its_colour_once(n0, patches):
+    for nz, ny, nx in _levels(n0, patches):
+        for color in (0, 1):
+            nxc = (nx - 1) // 2
+            bx, by, bz, tx, ty = _threads(_grid(nxc, ny - 2, nz - 2), (BX, BY))
+            z = bz + 1
+            y = by * BY + ty + 1
+            ok = y <= ny - 2
+            p = (color + y + z) & 1
+            x = (2 - p) + 2 * (bx * BX + tx)
+            ok &= x <= nx - 2
+            x, y, z = x[ok], y[ok], z[ok]
+            assert x.min() >= 1 and y.min() >= 1 and z.min() >= 1
+            hit = np.zeros((nz, ny, nx), int)
+            np.add.at(hit, (z, y, x), 1)
+            zz, yy, xx = np.indices((nz, ny, nx))
+            want = ((xx + yy + zz) % 2 == color) & (xx > 0) & (yy > 0) & (zz > 0) & (xx < nx - 1) & \
+                   (yy < ny - 1) & (zz < nz - 1)
+            assert np.array_equal(hit, want.astype(int))
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES)
+def test_ghost_kernel_covers_the_ghost_layer_once(n0, patches):
+    for nz, ny, nx in _levels(n0, patches)[1:]:
+        plane, ring = nx * ny, 2 * nx + 2 * (ny - 2)
+        total = 2 * plane + (nz - 2) * ring
+        t = np.arange((total + 255) // 256 * 256)
+        t = t[t < total]
+        z = np.where(t < plane, 0, nz - 1)
+        j = np.where(t < plane, t, t - plane)
+        y, x = j // nx, j % nx
+        s = t - 2 * plane
+        zr = 1 + s // ring
+        jr = s - (zr - 1) * ring
+        q = jr - 2 * nx
+        yr = np.where(jr < nx, 0, np.where(jr < 2 * nx, ny - 1, 1 + (q >> 1)))
+        xr = np.where(jr < nx, jr, np.where(jr < 2 * nx, jr - nx, np.where(q & 1, nx - 1, 0)))
+        face = t < 2 * plane
+        z, y, x = np.where(face, z, zr), np.where(face, y, yr), np.where(face, x, xr)
+        hit = np.zeros((nz, ny, nx), int)
+        np.add.at(hit, (z, y, x), 1)
+        ghost = np.ones((nz, ny, nx), int)
+        ghost[1:-1, 1:-1, 1:-1] = 0
+        assert np.array_equal(hit, ghost)
+
+
+def _interp_reads(x, y, z, c, m):
+    """Footprint indices the trilinear interpolation reads (parent node
+    origin + index, stored footprint at the index)."""
+    reads = []
+    for a in (0, 1):
+        for b in (0, 1):
+            for cc in (0, 1):
+                use = ((a == 0) | (x & 1 == 1)) & ((b == 0) | (y & 1 == 1)) & ((cc == 0) | (z & 1 == 1))
+                i, j, k = (x >> 1) + a, (y >> 1) + b, (z >> 1) + cc
+                reads.append((use, i, j, k))
+    return reads
+
+
+def _cubic_reads(x, y, z):
+    """Footprint indices (parent node origin + index) the cubic ghost
+    reconstruction reads: i0 - 1 .. i0 + 2 along odd axes, i0 along even."""
+    reads = []
+    for a in range(4):
+        for b in range(4):
+            for cc in range(4):
+                use = ((a == 0) | (x & 1 == 1)) & ((b == 0) | (y & 1 == 1)) & ((cc == 0) | (z & 1 == 1))
+                i = (x >> 1) + np.where(x & 1, a - 1, 0)
+                j = (y >> 1) + np.where(y & 1, b - 1, 0)
+                k = (z >> 1) + np.where(z & 1, cc - 1, 0)
+                reads.append((use, i, j, k))
+    return reads
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES)
+def test_transfer_kernels_stay_in_bounds(n0, patches):
+    shapes = _levels(n0, patches)
+    for lev, (c, m) in enumerate(patches):
+        pz, py, px = shapes[lev]
+        nz, ny, nx = shapes[lev + 1]
+        cz, cy, cx = c
+        mz, my, mx = m
+        # prolongation: every fine node, reads parent and the stored footprint
+        bx, by, bz, tx, ty = _threads(_grid(nx, ny, nz), (BX, BY))
+        z, y, x = bz, by * BY + ty, bx * BX + tx
+        ok = (y < ny) & (x < nx)
+        x, y, z = x[ok], y[ok], z[ok]
+        assert len(set(zip(x, y, z))) == nx * ny * nz
+        ghost = (x == 0) | (y == 0) | (z == 0) | (x == nx - 1) | (y == ny - 1) | (z == nz - 1)
+        for use, i, j, k in _interp_reads(x[~ghost], y[~ghost], z[~ghost], c, m):
+            i, j, k = i[use], j[use], k[use]
+            assert i.min() >= 0 and j.min() >= 0 and k.min() >= 0
+            assert i.max() <= mx and j.max() <= my and k.max() <= mz
+            assert (cx + i).max() <= px - 2 and (cy + j).max() <= py - 2 and (cz + k).max() <= pz - 2
+        # ghost nodes (here and in the ghost kernel): the cubic reads stay in
+        # the parent, one node beyond the footprint at most
+        for use, i, j, k in _cubic_reads(x[ghost], y[ghost], z[ghost]):
+            i, j, k = i[use], j[use], k[use]
+            if not i.size:
+                continue
+            assert i.min() >= -1 and j.min() >= -1 and k.min() >= -1
+            assert i.max() <= mx + 1 and j.max() <= my + 1 and k.max() <= mz + 1
+            assert min((cx + i).min(), (cy + j).min(), (cz + k).min()) >= 0
+            assert (cx + i).max() <= px - 1 and (cy + j).max() <= py - 1 and (cz + k).max() <= pz - 1
+        # restriction: every footprint node; the interior ones read the fine
+        # residual around node 2 i and the fine or parent neighbours
+        bx, by, bz, tx, ty = _threads(_grid(mx + 1, my + 1, mz + 1), (BX, BY))
+        k, j, i = bz, by * BY + ty, bx * BX + tx
+        ok = (j <= my) & (i <= mx)
+        i, j, k = i[ok], j[ok], k[ok]
+        assert len(set(zip(i, j, k))) == (mx + 1) * (my + 1) * (mz + 1)
+        inner = (i > 0) & (j > 0) & (k > 0) & (i < mx) & (j < my) & (k < mz)
+        fi, fj, fk = 2 * i[inner], 2 * j[inner], 2 * k[inner]
+        assert (fi - 1).min() >= 1 and (fi + 1).max() <= nx - 2
+        assert (fj - 1).min() >= 1 and (fj + 1).max() <= ny - 2
+        assert (fk - 1).min() >= 1 and (fk + 1).max() <= nz - 2
+        for di, dj, dk in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            a, b, cc = i[inner] + di, j[inner] + dj, k[inner] + dk
+            assert a.min() >= 0 and a.max() <= mx and b.max() <= my and cc.max() <= mz
+            inn = (a > 0) & (b > 0) & (cc > 0) & (a < mx) & (b < my) & (cc < mz)
+            assert (2 * a[inn]).max(initial=0) <= nx - 1
+            assert (cx + a[~inn]).max(initial=0) <= px - 1 and (cz + cc[~inn]).max(initial=0) <= pz - 1
+        # residual and norm: the unknowns of the level
+        bx, by, bz, tx, ty = _threads(_grid(nx - 2, ny - 2, nz - 2), (BX, BY))
+        z, y, x = bz + 1, by * BY + ty + 1, bx * BX + tx + 1
+        ok = (y <= ny - 2) & (x <= nx - 2)
+        assert len(set(zip(x[ok], y[ok], z[ok]))) == (nx - 2) * (ny - 2) * (nz - 2)
+        assert (z + 1).max() <= nz - 1
