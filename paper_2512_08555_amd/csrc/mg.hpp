@@ -26,6 +26,12 @@ hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp
 // set to (sum of its six neighbours - h^2 f) / 6
 hipError_t mg_smooth(bool f64, void* u, const void* f, MgGrid g, double h, int color, hipStream_t st);
 
+// nu red-black iterations on u, the same values as 2 nu half-steps: an odd
+// first one as two half-steps in place, then pairs of whole iterations
+// u -> s -> u by the fused kernel (s: a scratch array of the level's size)
+hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
+                                hipStream_t st);
+
 // r = f - Lap u on the unknowns (the ghost layer of r is not written)
 hipError_t mg_residual(bool f64, const void* u, const void* f, void* r, MgGrid g, double h, hipStream_t st);
 

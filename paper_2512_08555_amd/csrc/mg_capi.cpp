@@ -169,10 +169,8 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
     const MgGrid& gp = mg->grid[k - 1];
     const MgBox& b = mg->box[k - 1];
     e = mg_fill_ghosts(f64, u[k], g, u[k - 1], gp, b, st);
-    for (int it = 0; it < nu1 && e == hipSuccess; ++it) {
-      e = mg_smooth(f64, u[k], F[k], g, mg->h[k], 0, st);
-      if (e == hipSuccess) e = mg_smooth(f64, u[k], F[k], g, mg->h[k], 1, st);
-    }
+    // the residual buffer is the smoother's scratch until the residual
+    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], r, F[k], g, mg->h[k], nu1, st);
     if (e == hipSuccess) e = mg_residual(f64, u[k], F[k], r, g, mg->h[k], st);
     if (e == hipSuccess)
       e = mg_restrict(f64, u[k], r, g, u[k - 1], F[k - 1], wb + mg->off_uhat[k - 1], gp, b, mg->h[k - 1], st);
@@ -184,10 +182,7 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   for (int k = 1; k <= L && e == hipSuccess; ++k) {
     const MgGrid& g = mg->grid[k];
     e = mg_prolong(f64, u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1], mg->box[k - 1], st);
-    for (int it = 0; it < nu2 && e == hipSuccess; ++it) {
-      e = mg_smooth(f64, u[k], F[k], g, mg->h[k], 0, st);
-      if (e == hipSuccess) e = mg_smooth(f64, u[k], F[k], g, mg->h[k], 1, st);
-    }
+    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], r, F[k], g, mg->h[k], nu2, st);
   }
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   return set_error(UPS_OK, "");

@@ -8,6 +8,8 @@
 // weighting one axis at a time, z, then y, then x).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mg.hpp"
 
 namespace ups {
@@ -130,6 +132,142 @@ __global__ void __launch_bounds__(kBX * kBY) k_mg_rbgs(T* __restrict__ u, const 
   u[i] = (nb - h2 * f[i]) / T(6);
 }
 
+// One whole red-black iteration from uin into uout (two different arrays),
+// the same arithmetic as a red half-step followed by a black one.  A block
+// owns a tile of 64 (x) by TY (y) nodes and a chunk of kZC planes, and
+// marches up z with rings of planes in LDS: u_in with a halo of 2, the
+// half-updated values H (red unknowns new, every other node as in u_in)
+// with a halo of 1, and f.  H of plane p is computed on the tile and its
+// halo from u_in (the halo's red values again, so no block reads what
+// another writes); the black unknowns of plane p - 1 then follow from H of
+// planes p - 2 .. p.  Every node of the tile, ghost layer included, is
+// written to uout.  The chunk starts two planes early to fill the rings,
+// and the next plane's loads are in flight while the current one is
+// updated.
+constexpr int kZC = 32;
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(256) k_mg_gs2(const T* __restrict__ uin, T* __restrict__ uout,
+                                                const T* __restrict__ f, MgGrid g, T h2) {
+  constexpr int TX = 64;
+  constexpr int UX = TX + 4, UY = TY + 4;
+  constexpr int HX = TX + 2, HY = TY + 2;
+  constexpr int NU = (UX * UY + 255) / 256;   // u_in values each thread stages per plane
+  constexpr int NH = (HX * HY + 255) / 256;   // f and H values per thread
+  constexpr int NB = TX * TY / 256;           // outputs per thread
+  __shared__ T U[3][UY][UX];
+  __shared__ T H[3][HY][HX];
+  __shared__ T F[3][HY][HX];   // three slots: f of p + 1 is staged while black reads f of p - 1
+  // XCD-aware tile order: blocks are dealt to the 8 XCDs in turn, so block
+  // b runs on XCD b % 8; each XCD takes one contiguous run of tiles ordered
+  // y fastest, then x, then z chunk, and tiles that share halo rows run on
+  // the same XCD (its L2) at about the same time.
+  const int nty = (g.ny + TY - 1) / TY, ntx = (g.nx + TX - 1) / TX;
+  const int ntiles = nty * ntx * ((g.nz + kZC - 1) / kZC);
+  const int per_xcd = (ntiles + 7) / 8;
+  const int unit = int(blockIdx.x % 8) * per_xcd + int(blockIdx.x / 8);
+  if (unit >= ntiles) return;
+  const int tyi = unit % nty, txi = (unit / nty) % ntx, tzi = unit / (nty * ntx);
+  const int tid = threadIdx.y * kBX + threadIdx.x;
+  const int x0 = txi * TX, y0 = tyi * TY;
+  const int zs = tzi * kZC, ze = min(zs + kZC, g.nz);
+  const size_t sy = g.nx, sz = (size_t)g.nx * g.ny;
+  auto in_grid = [&](int x, int y, int z) {
+    return z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
+  };
+  auto unknown = [&](int x, int y, int z) {
+    return z >= 1 && z <= g.nz - 2 && y >= 1 && y <= g.ny - 2 && x >= 1 && x <= g.nx - 2;
+  };
+  // plane p of u_in (halo 2) and of f (halo 1) into registers; the loads
+  // are issued here and waited for only when the registers go to LDS
+  T ru[NU], rf[NH];
+  auto fetch = [&](int pu, int pf) {
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int e = tid + 256 * t;
+      const int ly = e / UX, lx = e - ly * UX;
+      const int x = x0 - 2 + lx, y = y0 - 2 + ly;
+      ru[t] = (e < UX * UY && in_grid(x, y, pu)) ? uin[(size_t)pu * sz + (size_t)y * sy + x] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int e = tid + 256 * t;
+      const int ly = e / HX, lx = e - ly * HX;
+      const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+      rf[t] = (e < HX * HY && in_grid(x, y, pf)) ? f[(size_t)pf * sz + (size_t)y * sy + x] : T(0);
+    }
+  };
+  auto stage = [&](int pu, int pf) {
+    T(*du)[UX] = U[(pu + 6) % 3];
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int e = tid + 256 * t;
+      if (e < UX * UY) du[e / UX][e % UX] = ru[t];
+    }
+    T(*df)[HX] = F[(pf + 6) % 3];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int e = tid + 256 * t;
+      if (e < HX * HY) df[e / HX][e % HX] = rf[t];
+    }
+  };
+  auto red = [&](int p) {
+    const T(*Um)[UX] = U[(p + 5) % 3];
+    const T(*U0)[UX] = U[(p + 6) % 3];
+    const T(*Up)[UX] = U[(p + 7) % 3];
+    const T(*Fp)[HX] = F[(p + 6) % 3];
+    T(*Hd)[HX] = H[(p + 6) % 3];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int e = tid + 256 * t;
+      if (e >= HX * HY) break;
+      const int ly = e / HX, lx = e - ly * HX;
+      const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+      const int ux = lx + 1, uy = ly + 1;
+      T v = U0[uy][ux];
+      if (unknown(x, y, p) && ((x + y + p) & 1) == 0) {
+        const T nb = Up[uy][ux] + Um[uy][ux] + U0[uy + 1][ux] + U0[uy - 1][ux] + U0[uy][ux + 1] + U0[uy][ux - 1];
+        v = (nb - h2 * Fp[ly][lx]) / T(6);
+      }
+      Hd[ly][lx] = v;
+    }
+  };
+  auto black = [&](int q) {
+    const T(*Hm)[HX] = H[(q + 5) % 3];
+    const T(*H0)[HX] = H[(q + 6) % 3];
+    const T(*Hp)[HX] = H[(q + 7) % 3];
+    const T(*Fq)[HX] = F[(q + 6) % 3];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int e = tid + 256 * t;
+      const int ly = e / TX, lx = e - ly * TX;
+      const int x = x0 + lx, y = y0 + ly;
+      if (x >= g.nx || y >= g.ny) continue;
+      const int hx = lx + 1, hy = ly + 1;
+      T v = H0[hy][hx];
+      if (unknown(x, y, q) && ((x + y + q) & 1) == 1) {
+        const T nb = Hp[hy][hx] + Hm[hy][hx] + H0[hy + 1][hx] + H0[hy - 1][hx] + H0[hy][hx + 1] + H0[hy][hx - 1];
+        v = (nb - h2 * Fq[hy][hx]) / T(6);
+      }
+      uout[(size_t)q * sz + (size_t)y * sy + x] = v;
+    }
+  };
+  // prologue: u_in planes zs - 2 and zs - 1 staged, zs and f of zs - 1 in flight
+  fetch(zs - 2, zs - 1);
+  stage(zs - 2, zs - 1);
+  fetch(zs - 1, zs - 1);
+  stage(zs - 1, zs - 1);
+  fetch(zs, zs - 1);
+  for (int p = zs - 1; p <= ze; ++p) {
+    stage(p + 1, p);          // u_in of p + 1, f of p
+    fetch(p + 2, p + 1);      // in flight during the updates below
+    __syncthreads();
+    red(p);
+    __syncthreads();
+    if (p - 1 >= zs) black(p - 1);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T residual_at(const T* __restrict__ u, const T* __restrict__ f, size_t i, size_t sy,
                                          size_t sz, T h2) {
@@ -189,32 +327,72 @@ __global__ void __launch_bounds__(kBX * kBY) k_mg_restrict(const T* __restrict__
   uhat[ih] = ui;
 }
 
+// One thread per coarse footprint node (i, j, k): it updates the fine
+// unknowns 2 (i, j, k) + (a, b, c), a, b, c in {0, 1} (only 0 where the
+// index is m), from the correction at the corners of its coarse cell, so
+// neighbouring threads write neighbouring fine pairs and share their
+// corner loads.  Fine nodes on the ghost layer are left to the ghost kernel.
 template <typename T>
 __global__ void __launch_bounds__(kBX * kBY) k_mg_prolong(T* __restrict__ u, MgGrid g, const T* __restrict__ up,
                                                           const T* __restrict__ uhat, MgGrid gp, MgBox b) {
-  const int z = blockIdx.z;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  if (y >= g.ny || x >= g.nx) return;
-  const size_t i = lin(x, y, z, g);
-  if (is_ghost(x, y, z, g))
-    u[i] = interp_cubic(up, gp, b, x, y, z);
-  else
-    u[i] += interp_lin(up, uhat, gp, b, x, y, z);
+  const int k = blockIdx.z;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  if (j > b.my || i > b.mx) return;
+  // corners (i + di, j + dj, k + dk); where the index is m the far corner
+  // is not needed and is clamped to the near one
+  const int i1 = i < b.mx ? i + 1 : i, j1 = j < b.my ? j + 1 : j, k1 = k < b.mz ? k + 1 : k;
+  const int ci[2] = {i, i1}, cj[2] = {j, j1}, ck[2] = {k, k1};
+  T E[2][2][2];   // [dk][dj][di]
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di)
+        E[dk][dj][di] = up[lin(b.ox + ci[di], b.oy + cj[dj], b.oz + ck[dk], gp)] -
+                        uhat[((size_t)ck[dk] * (b.my + 1) + cj[dj]) * (b.mx + 1) + ci[di]];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int z = 2 * k + c;
+    if (z == 0 || z >= g.nz - 1) continue;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const int y = 2 * j + bb;
+      if (y == 0 || y >= g.ny - 1) continue;
+      T yv[2];   // at the x corners: along z, then y
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const T z0 = c ? T(0.5) * (E[0][0][di] + E[1][0][di]) : E[0][0][di];
+        const T z1 = c ? T(0.5) * (E[0][1][di] + E[1][1][di]) : E[0][1][di];
+        yv[di] = bb ? T(0.5) * (z0 + z1) : z0;
+      }
+      const size_t row = ((size_t)z * g.ny + y) * g.nx;
+      if (i > 0 && i < b.mx) u[row + 2 * i] += yv[0];
+      if (i < b.mx) u[row + 2 * i + 1] += T(0.5) * (yv[0] + yv[1]);
+    }
+  }
 }
 
+// Max |f - Lap u| over the unknowns outside the child's footprint interior:
+// a grid-stride loop over rows (4 per block pass, 64 threads along x), a
+// reduction in the block, one atomic per block.
 template <typename T>
 __global__ void __launch_bounds__(kBX * kBY) k_mg_resnorm(const T* __restrict__ u, const T* __restrict__ f, MgGrid g,
                                                           T h2, MgBox ch, int has_child,
                                                           unsigned long long* __restrict__ out) {
-  const int z = blockIdx.z + 1;
-  const int y = blockIdx.y * kBY + threadIdx.y + 1;
-  const int x = blockIdx.x * kBX + threadIdx.x + 1;
+  const long long rows = (long long)(g.ny - 2) * (g.nz - 2);
+  const size_t sy = g.nx, sz = (size_t)g.nx * g.ny;
   double v = 0.0;
-  if (y <= g.ny - 2 && x <= g.nx - 2) {
-    const bool skip = has_child && x > ch.ox && x < ch.ox + ch.mx && y > ch.oy && y < ch.oy + ch.my && z > ch.oz &&
-                      z < ch.oz + ch.mz;
-    if (!skip) v = fabs((double)residual_at(u, f, lin(x, y, z, g), (size_t)g.nx, (size_t)g.nx * g.ny, h2));
+  for (long long r = (long long)blockIdx.x * kBY + threadIdx.y; r < rows; r += (long long)gridDim.x * kBY) {
+    const int z = 1 + int(r / (g.ny - 2));
+    const int y = 1 + int(r - (long long)(z - 1) * (g.ny - 2));
+    const bool yz_in = has_child && y > ch.oy && y < ch.oy + ch.my && z > ch.oz && z < ch.oz + ch.mz;
+    for (int x = 1 + threadIdx.x; x <= g.nx - 2; x += kBX) {
+      if (yz_in && x > ch.ox && x < ch.ox + ch.mx) continue;
+      const double e = fabs((double)residual_at(u, f, lin(x, y, z, g), sy, sz, h2));
+      v = e > v || e != e ? e : v;
+    }
   }
   // non-negative doubles order like their bit patterns (NaN above all)
   unsigned long long bits = (unsigned long long)__double_as_longlong(v);
@@ -222,7 +400,13 @@ __global__ void __launch_bounds__(kBX * kBY) k_mg_resnorm(const T* __restrict__ 
     const unsigned long long w = __shfl_xor(bits, o, 64);
     bits = w > bits ? w : bits;
   }
-  if (((threadIdx.y * kBX + threadIdx.x) & 63) == 0 && bits) atomicMax(out, bits);
+  __shared__ unsigned long long wmax[kBY];
+  if (threadIdx.x == 0) wmax[threadIdx.y] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    for (int w = 1; w < kBY; ++w) bits = wmax[w] > bits ? wmax[w] : bits;
+    if (bits) atomicMax(out, bits);
+  }
 }
 
 __global__ void k_mg_zero(double* p, int n) {
@@ -260,6 +444,34 @@ hipError_t mg_smooth(bool f64, void* u, const void* f, MgGrid g, double h, int c
   return hipGetLastError();
 }
 
+hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
+                                hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (nu & 1) {
+    e = mg_smooth(f64, u, f, g, h, 0, st);
+    if (e == hipSuccess) e = mg_smooth(f64, u, f, g, h, 1, st);
+  }
+  constexpr int TY64 = 8, TY32 = 8;
+  const int ty = f64 ? TY64 : TY32;
+  const long long ntiles = (long long)((g.nx + 63) / 64) * ((g.ny + ty - 1) / ty) * ((g.nz + kZC - 1) / kZC);
+  const dim3 grid(unsigned(8 * ((ntiles + 7) / 8)));
+  const dim3 block(kBX, kBY);
+  for (int it = 0; it < nu / 2 && e == hipSuccess; ++it) {
+    for (int half = 0; half < 2 && e == hipSuccess; ++half) {
+      const void* a = half ? s : u;
+      void* b = half ? u : s;
+      if (f64)
+        hipLaunchKernelGGL((k_mg_gs2<double, TY64>), grid, block, 0, st, static_cast<const double*>(a),
+                           static_cast<double*>(b), static_cast<const double*>(f), g, h * h);
+      else
+        hipLaunchKernelGGL((k_mg_gs2<float, TY32>), grid, block, 0, st, static_cast<const float*>(a),
+                           static_cast<float*>(b), static_cast<const float*>(f), g, float(h * h));
+      e = hipGetLastError();
+    }
+  }
+  return e;
+}
+
 hipError_t mg_residual(bool f64, const void* u, const void* f, void* r, MgGrid g, double h, hipStream_t st) {
   const dim3 grid = grid_xyz(g.nx - 2, g.ny - 2, g.nz - 2), block(kBX, kBY);
   if (f64)
@@ -287,19 +499,21 @@ hipError_t mg_restrict(bool f64, const void* u, const void* r, MgGrid g, void* u
 
 hipError_t mg_prolong(bool f64, void* u, MgGrid g, const void* up, const void* uhat, MgGrid gp, MgBox b,
                       hipStream_t st) {
-  const dim3 grid = grid_xyz(g.nx, g.ny, g.nz), block(kBX, kBY);
+  const dim3 grid = grid_xyz(b.mx + 1, b.my + 1, b.mz + 1), block(kBX, kBY);
   if (f64)
     hipLaunchKernelGGL(k_mg_prolong<double>, grid, block, 0, st, static_cast<double*>(u), g,
                        static_cast<const double*>(up), static_cast<const double*>(uhat), gp, b);
   else
     hipLaunchKernelGGL(k_mg_prolong<float>, grid, block, 0, st, static_cast<float*>(u), g,
                        static_cast<const float*>(up), static_cast<const float*>(uhat), gp, b);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? mg_fill_ghosts(f64, u, g, up, gp, b, st) : e;
 }
 
 hipError_t mg_residual_norm(bool f64, const void* u, const void* f, MgGrid g, double h, const MgBox* child,
                             double* out, hipStream_t st) {
-  const dim3 grid = grid_xyz(g.nx - 2, g.ny - 2, g.nz - 2), block(kBX, kBY);
+  const long long rows = (long long)(g.ny - 2) * (g.nz - 2);
+  const dim3 grid(unsigned(std::min<long long>((rows + kBY - 1) / kBY, 2048))), block(kBX, kBY);
   const MgBox ch = child ? *child : MgBox{0, 0, 0, 0, 0, 0};
   unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
   if (f64)

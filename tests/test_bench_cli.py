@@ -23,4 +23,6 @@ def test_committed_traffic_record_is_well_formed():
     assert isinstance(rec.get("source_hash"), str) and rec["source_hash"]
     assert rec["kernels"]
     for name, ent in rec["kernels"].items():
-        assert float(ent["bytes_per_launch"]) > 0, name
+        # bytes of the main launch of a column pass, or of every launch
+        b = ent.get("main_launch_bytes", ent.get("bytes_per_launch"))
+        assert b is not None and float(b) > 0, name

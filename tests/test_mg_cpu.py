@@ -143,19 +143,6 @@ def test_ghost_kernel_covers_the_ghost_layer_once(n0, patches):
         assert np.array_equal(hit, ghost)
 
 
-def _interp_reads(x, y, z, c, m):
-    """Footprint indices the trilinear interpolation reads (parent node
-    origin + index, stored footprint at the index)."""
-    reads = []
-    for a in (0, 1):
-        for b in (0, 1):
-            for cc in (0, 1):
-                use = ((a == 0) | (x & 1 == 1)) & ((b == 0) | (y & 1 == 1)) & ((cc == 0) | (z & 1 == 1))
-                i, j, k = (x >> 1) + a, (y >> 1) + b, (z >> 1) + cc
-                reads.append((use, i, j, k))
-    return reads
-
-
 def _cubic_reads(x, y, z):
     """Footprint indices (parent node origin + index) the cubic ghost
     reconstruction reads: i0 - 1 .. i0 + 2 along odd axes, i0 along even."""
@@ -179,28 +166,42 @@ def test_transfer_kernels_stay_in_bounds(n0, patches):
         nz, ny, nx = shapes[lev + 1]
         cz, cy, cx = c
         mz, my, mx = m
-        # prolongation: every fine node, reads parent and the stored footprint
-        bx, by, bz, tx, ty = _threads(_grid(nx, ny, nz), (BX, BY))
-        z, y, x = bz, by * BY + ty, bx * BX + tx
-        ok = (y < ny) & (x < nx)
-        x, y, z = x[ok], y[ok], z[ok]
-        assert len(set(zip(x, y, z))) == nx * ny * nz
-        ghost = (x == 0) | (y == 0) | (z == 0) | (x == nx - 1) | (y == ny - 1) | (z == nz - 1)
-        for use, i, j, k in _interp_reads(x[~ghost], y[~ghost], z[~ghost], c, m):
-            i, j, k = i[use], j[use], k[use]
-            assert i.min() >= 0 and j.min() >= 0 and k.min() >= 0
-            assert i.max() <= mx and j.max() <= my and k.max() <= mz
-            assert (cx + i).max() <= px - 2 and (cy + j).max() <= py - 2 and (cz + k).max() <= pz - 2
-        # ghost nodes (here and in the ghost kernel): the cubic reads stay in
-        # the parent, one node beyond the footprint at most
-        for use, i, j, k in _cubic_reads(x[ghost], y[ghost], z[ghost]):
-            i, j, k = i[use], j[use], k[use]
-            if not i.size:
+        # prolongation: one thread per footprint node (i, j, k) writes the fine
+        # unknowns 2 (i, j, k) + (a, b, c) (a = 0 only where i = m), never a
+        # ghost node, each unknown exactly once; it reads the cell corners
+        bx, by, bz, tx, ty = _threads(_grid(mx + 1, my + 1, mz + 1), (BX, BY))
+        k, j, i = bz, by * BY + ty, bx * BX + tx
+        ok = (j <= my) & (i <= mx)
+        i, j, k = i[ok], j[ok], k[ok]
+        hit = np.zeros((nz, ny, nx), int)
+        for c_ in (0, 1):
+            for b_ in (0, 1):
+                for a_ in (0, 1):
+                    live = ((a_ == 0) | (i < mx)) & ((b_ == 0) | (j < my)) & ((c_ == 0) | (k < mz))
+                    x, y, z = 2 * i + a_, 2 * j + b_, 2 * k + c_
+                    zok = (z > 0) & (z < nz - 1) & (y > 0) & (y < ny - 1)
+                    xok = np.where(a_ == 0, (i > 0) & (i < mx), True)
+                    w = live & zok & xok
+                    np.add.at(hit, (z[w], y[w], x[w]), 1)
+                    # corners read: (i + a_, j + b_, k + c_) where live
+                    assert (i + a_)[live].max() <= mx and (cx + i + a_)[live].max() <= px - 2
+                    assert (j + b_)[live].max() <= my and (k + c_)[live].max() <= mz
+        inner = np.zeros((nz, ny, nx), int)
+        inner[1:-1, 1:-1, 1:-1] = 1
+        assert np.array_equal(hit, inner)
+        # ghost nodes (ghost kernel): the cubic reads stay in the parent, one
+        # node beyond the footprint at most
+        zz, yy, xx = np.indices((nz, ny, nx))
+        ghost = inner == 0
+        x, y, z = xx[ghost], yy[ghost], zz[ghost]
+        for use, i2, j2, k2 in _cubic_reads(x, y, z):
+            i2, j2, k2 = i2[use], j2[use], k2[use]
+            if not i2.size:
                 continue
-            assert i.min() >= -1 and j.min() >= -1 and k.min() >= -1
-            assert i.max() <= mx + 1 and j.max() <= my + 1 and k.max() <= mz + 1
-            assert min((cx + i).min(), (cy + j).min(), (cz + k).min()) >= 0
-            assert (cx + i).max() <= px - 1 and (cy + j).max() <= py - 1 and (cz + k).max() <= pz - 1
+            assert i2.min() >= -1 and j2.min() >= -1 and k2.min() >= -1
+            assert i2.max() <= mx + 1 and j2.max() <= my + 1 and k2.max() <= mz + 1
+            assert min((cx + i2).min(), (cy + j2).min(), (cz + k2).min()) >= 0
+            assert (cx + i2).max() <= px - 1 and (cy + j2).max() <= py - 1 and (cz + k2).max() <= pz - 1
         # restriction: every footprint node; the interior ones read the fine
         # residual around node 2 i and the fine or parent neighbours
         bx, by, bz, tx, ty = _threads(_grid(mx + 1, my + 1, mz + 1), (BX, BY))
@@ -225,3 +226,51 @@ def test_transfer_kernels_stay_in_bounds(n0, patches):
         ok = (y <= ny - 2) & (x <= nx - 2)
         assert len(set(zip(x[ok], y[ok], z[ok]))) == (nx - 2) * (ny - 2) * (nz - 2)
         assert (z + 1).max() <= nz - 1
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES)
+def test_residual_norm_rows_cover_the_unknowns_once(n0, patches):
+    for nz, ny, nx in _levels(n0, patches):
+        rows = (ny - 2) * (nz - 2)
+        grid = min((rows + BY - 1) // BY, 2048)
+        seen = np.zeros((nz, ny), int)
+        for blk in range(grid):
+            for ty in range(BY):
+                r = np.arange(blk * BY + ty, rows, grid * BY)
+                z = 1 + r // (ny - 2)
+                y = 1 + r - (z - 1) * (ny - 2)
+                np.add.at(seen, (z, y), 1)
+        want = np.zeros((nz, ny), int)
+        want[1:-1, 1:-1] = 1
+        assert np.array_equal(seen, want)
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), [])])
+@pytest.mark.parametrize("ty", [8, 16])
+def test_fused_smoothing_tiles_cover_the_level_once(n0, patches, ty):
+    # the fused red-black iteration: tiles of 64 x TY nodes by chunks of 32
+    # planes write every node once; the LDS regions (u_in with a halo of 2,
+    # H and f with a halo of 1) hold every neighbour the updates read
+    TX, ZC = 64, 32
+    UX, UY, HX, HY = TX + 4, ty + 4, TX + 2, ty + 2
+    for nz, ny, nx in _levels(n0, patches):
+        hit = np.zeros((nz, ny, nx), int)
+        nty, ntx = (ny + ty - 1) // ty, (nx + TX - 1) // TX
+        ntiles = nty * ntx * ((nz + ZC - 1) // ZC)
+        per_xcd = (ntiles + 7) // 8
+        for b in range(8 * per_xcd):          # the launch: 8 per_xcd blocks
+            unit = (b % 8) * per_xcd + b // 8
+            if unit >= ntiles:
+                continue
+            tyi, txi, tzi = unit % nty, (unit // nty) % ntx, unit // (nty * ntx)
+            zs, ze = tzi * ZC, min(tzi * ZC + ZC, nz)
+            x = txi * TX + np.arange(TX)
+            y = tyi * ty + np.arange(ty)
+            x, y = x[x < nx], y[y < ny]
+            hit[zs:ze, y[0]:y[-1] + 1, x[0]:x[-1] + 1] += 1
+        assert (hit == 1).all()
+        # red at H position (lx, ly) reads U at (lx + 1 +- 1, ly + 1 +- 1)
+        lx, ly = np.meshgrid(np.arange(HX), np.arange(HY))
+        assert (lx + 2).max() <= UX - 1 and (ly + 2).max() <= UY - 1 and lx.min() >= 0
+        # black at tile position reads H at (lx + 1 +- 1, ly + 1 +- 1)
+        assert TX + 1 <= HX - 1 and ty + 1 <= HY - 1
