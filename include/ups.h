@@ -332,10 +332,11 @@ ups_status ups_plan_destroy(ups_plan_t plan);
 /* ---- batches ------------------------------------------------------------
  * A batch runs `count` independent problems (any shapes, precisions and
  * component counts; at most 200) as ONE hipGraph launch: for each of the
- * five passes the problems sharing a compiled kernel run in one grouped
- * launch, the grouped launches of a pass are parallel graph branches, and
- * the passes follow each other.  Results equal those of ups_solve on each
- * problem with the same kernel variants. */
+ * five passes the problems sharing a compiled kernel run in grouped
+ * launches (a group above a quarter of the pass's algorithmic bytes is
+ * split), the launches of a pass are dealt longest first to four parallel
+ * chains of the graph, and the passes follow each other.  Results equal
+ * those of ups_solve on each problem with the same kernel variants. */
 
 /* Validate every problem and lay out the batch (host only).  Errors as
  * ups_plan_create for the first failing problem; UNSUPPORTED above 200. */
@@ -356,7 +357,7 @@ ups_status ups_batch_setup(ups_batch_t batch, void* green, size_t green_bytes, v
  * then the graph is launched on `stream`. */
 ups_status ups_batch_solve(ups_batch_t batch, const void* const* f, void* const* u, void* stream);
 
-/* Number of grouped launches the batch uses for pass 0..4. */
+/* Number of grouped launches (over all chains) the batch uses for pass 0..4. */
 int ups_batch_launches(ups_batch_t batch, int pass);
 
 ups_status ups_batch_destroy(ups_batch_t batch);

@@ -1,11 +1,17 @@
 // Batched solves: many independent problems (uneven shapes, vector
 // right-hand sides) run as ONE hipGraph launch of grouped pass kernels.
 //
-// For each pass, the problems that use the same compiled kernel form one
-// grouped launch (the kernel finds its problem from a block -> entry map);
-// the launches of one pass are parallel branches of the graph and the five
-// passes are joined in order.  The caller's f and u pointers are written to
-// a small device table by one kernel per call, so the graph itself never
+// For each pass, the problems that use the same compiled kernel form
+// grouped launches (the kernel finds its problem from a block -> entry map);
+// a group whose algorithmic bytes exceed a quarter of the pass's is split
+// into several launches.  The launches of a pass are dealt, longest first
+// by bytes, to the least loaded of kChains chains; the chains are parallel
+// branches of the graph, each a sequence of launches, and the five passes
+// are joined in order.  (Left to the runtime, ten or more branches per pass
+// are spread over the process's hardware queues in capture order, and the
+// two longest launches of a pass can land on the same queue, one after the
+// other, while the others idle.)  The caller's f and u pointers are written
+// to a small device table by one kernel per call, so the graph itself never
 // changes between solves.
 #include <hip/hip_runtime.h>
 
@@ -26,6 +32,8 @@ using namespace ups;
 namespace {
 
 constexpr int kMaxBatch = 200;
+// parallel chains per pass: the hardware queues a process gets by default
+constexpr int kChains = 4;
 
 struct IoPtrs {
   const void* p[2 * kMaxBatch];
@@ -40,6 +48,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Launch {
   const PassVariant* var;
+  double bytes = 0;              // algorithmic bytes of its problems in this pass
   std::vector<int> probs;        // problem indices in this group
   size_t off_ents = 0, off_bmap = 0;
   unsigned nblocks = 0;
@@ -55,6 +64,7 @@ struct ups_batch_s {
   std::vector<std::array<const PassVariant*, 5>> var;
   std::vector<size_t> off_green, off_work;
   std::vector<Launch> launches[5];
+  std::vector<int> chains[5][kChains];   // launch indices of each chain, in order
   size_t off_tables = 0, off_io = 0;
   size_t green_bytes = 0, work_bytes = 0;
   void* green = nullptr;
@@ -114,20 +124,53 @@ ups_status ups_batch_create(const ups_problem* probs, int count, ups_batch_t* ou
     work_off = align_up(work_off + g.solve_work, 256);
     setup_max = std::max(setup_max, g.work_bytes);
   }
-  // group problems per pass by kernel variant
+  // group problems per pass by kernel variant, split groups above a quarter
+  // of the pass's bytes, and deal the launches to the chains longest first
   for (int k = 0; k < 5; ++k) {
-    std::map<const PassVariant*, int> idx;
+    std::map<const PassVariant*, std::vector<int>> groups;
+    double total = 0;
     for (int i = 0; i < count; ++i) {
-      const PassVariant* v = b->var[i][k];
-      auto it = idx.find(v);
-      if (it == idx.end()) {
-        idx[v] = int(b->launches[k].size());
-        Launch L;
-        L.var = v;
-        b->launches[k].push_back(L);
-        it = idx.find(v);
+      groups[b->var[i][k]].push_back(i);
+      total += model_bytes(b->geo[i], k);
+    }
+    const double cap = total / kChains;
+    for (auto& kv : groups) {
+      std::vector<int>& ps = kv.second;
+      std::stable_sort(ps.begin(), ps.end(), [&](int a, int c) {
+        return model_bytes(b->geo[a], k) > model_bytes(b->geo[c], k);
+      });
+      // first fit, largest problem first, into launches of at most `cap`
+      // bytes (a larger problem gets a launch of its own)
+      std::vector<Launch> pieces;
+      for (int i : ps) {
+        const double c = model_bytes(b->geo[i], k);
+        Launch* dst = nullptr;
+        for (Launch& L : pieces)
+          if (L.bytes + c <= cap) {
+            dst = &L;
+            break;
+          }
+        if (!dst) {
+          pieces.emplace_back();
+          dst = &pieces.back();
+          dst->var = kv.first;
+        }
+        dst->probs.push_back(i);
+        dst->bytes += c;
       }
-      b->launches[k][it->second].probs.push_back(i);
+      for (Launch& L : pieces) b->launches[k].push_back(std::move(L));
+    }
+    std::vector<int> order(b->launches[k].size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = int(j);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return b->launches[k][a].bytes > b->launches[k][c].bytes; });
+    double load[kChains] = {};
+    for (int j : order) {
+      int best = 0;
+      for (int c = 1; c < kChains; ++c)
+        if (load[c] < load[best]) best = c;
+      b->chains[k][best].push_back(j);
+      load[best] += b->launches[k][j].bytes;
     }
     for (Launch& L : b->launches[k]) {
       unsigned block = 0;
@@ -206,9 +249,7 @@ ups_status ups_batch_setup(ups_batch_t b, void* green, size_t green_bytes, void*
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   // descriptor tables
   const void* const* io = reinterpret_cast<const void* const*>(gb + b->off_io);
-  size_t max_par = 1;
   for (int k = 0; k < 5; ++k) {
-    max_par = std::max(max_par, b->launches[k].size());
     for (Launch& L : b->launches[k]) {
       for (int j = 0; j < int(L.probs.size()); ++j) {
         const int i = L.probs[j];
@@ -227,13 +268,13 @@ ups_status ups_batch_setup(ups_batch_t b, void* green, size_t green_bytes, void*
       if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
     }
   }
-  // the graph: five joined stages, one branch per grouped launch
-  for (size_t i = 0; i < max_par + 1 && e == hipSuccess; ++i) {
+  // the graph: five joined stages, one branch per chain of grouped launches
+  for (int i = 0; i < kChains + 1 && e == hipSuccess; ++i) {
     hipStream_t s2;
     e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
     if (e == hipSuccess) b->streams.push_back(s2);
   }
-  for (size_t i = 0; i < 5 * (max_par + 1) && e == hipSuccess; ++i) {
+  for (int i = 0; i < 5 * (kChains + 1) && e == hipSuccess; ++i) {
     hipEvent_t ev;
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) b->events.push_back(ev);
@@ -245,16 +286,19 @@ ups_status ups_batch_setup(ups_batch_t b, void* green, size_t green_bytes, void*
   for (int k = 0; k < 5 && e == hipSuccess; ++k) {
     hipEvent_t fork = b->events[ev_i++];
     e = hipEventRecord(fork, cap);
-    for (size_t j = 0; j < b->launches[k].size() && e == hipSuccess; ++j) {
-      Launch& L = b->launches[k][j];
-      hipStream_t sj = b->streams[1 + j];
-      e = hipStreamWaitEvent(sj, fork, 0);
-      GroupArgs ga{reinterpret_cast<const GroupEntry*>(gb + L.off_ents),
-                   reinterpret_cast<const unsigned short*>(gb + L.off_bmap), io};
-      if (e == hipSuccess) L.var->launch_grouped(ga, L.nblocks, sj);
-      if (e == hipSuccess) e = hipGetLastError();
+    for (int c = 0; c < kChains && e == hipSuccess; ++c) {
+      if (b->chains[k][c].empty()) continue;
+      hipStream_t sc = b->streams[1 + c];
+      e = hipStreamWaitEvent(sc, fork, 0);
+      for (size_t q = 0; q < b->chains[k][c].size() && e == hipSuccess; ++q) {
+        Launch& L = b->launches[k][b->chains[k][c][q]];
+        GroupArgs ga{reinterpret_cast<const GroupEntry*>(gb + L.off_ents),
+                     reinterpret_cast<const unsigned short*>(gb + L.off_bmap), io};
+        L.var->launch_grouped(ga, L.nblocks, sc);
+        e = hipGetLastError();
+      }
       hipEvent_t join = b->events[ev_i++];
-      if (e == hipSuccess) e = hipEventRecord(join, sj);
+      if (e == hipSuccess) e = hipEventRecord(join, sc);
       if (e == hipSuccess) e = hipStreamWaitEvent(cap, join, 0);
     }
   }
