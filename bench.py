@@ -343,17 +343,22 @@ def main():
     value = n ** 3 / (step_ms * 1e-3)
     dom = int(np.argmax(per_pass))
     dom_name = plan.kernel(dom)
-    # A column pass (1-3) runs one main launch over the first kmain of the kx
-    # x-frequency columns (a multiple of 8 XCDs x the columns of one 128-byte
+    # With column 0 carrying the Nyquist column (ups_plan_nyquist_packed, the
+    # 512^3 FP32 plan), each column pass runs one launch over its kx - 1
+    # columns, the z pass with its pair launch for column 0 beside it, joined
+    # before the pass ends: the events around the pass time all of it, and
+    # its algorithmic bytes are the whole pass's (all kx x-frequencies).
+    # Otherwise a column pass (1-3) runs one main launch over the first kmain
+    # of the kx columns (a multiple of 8 XCDs x the columns of one 128-byte
     # line) and a narrow launch over the rest on the plan's second stream,
-    # alongside it; the events around the pass on the caller's stream
-    # therefore time the main launch.  Every term of a column pass's byte
-    # model is linear in the number of columns, so the main launch's
-    # algorithmic bytes are the pass's times kmain / kx.
+    # alongside it; the events then time the main launch.  Every term of a
+    # column pass's byte model is linear in the number of columns, so the
+    # main launch's algorithmic bytes are the pass's times kmain / kx.
+    packed = plan.nyquist_packed
     m = 2 * n
     kx = m // 2 + 1
     align = 8 * (128 // 8)   # 8 XCDs x 16 complex floats per 128-byte line
-    kzm = kx // align * align
+    kzm = kx if packed else kx // align * align
     kmain = kzm if dom in (1, 2, 3) else kx
     dom_bytes = plan.model_bytes(dom) * kmain / kx
     achieved = dom_bytes / (per_pass[dom] * 1e-3) / 1e9
@@ -444,7 +449,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name,
                      "launch_ms": round(float(per_pass[dom]), 4),
                      "algorithmic_bytes_per_launch": dom_bytes,
-                     "columns_per_launch": "%d of %d" % (kmain, kx)},
+                     "columns_per_launch": ("all %d (column 0 carries the Nyquist column)" % kx if packed
+                                            else "%d of %d" % (kmain, kx))},
         "cpu_baseline": cpu,
     }
     out.update(extra)

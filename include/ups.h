@@ -269,9 +269,25 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name);
  * ups_plan_create picks a default from the problem size (FP64 with at least
  * 384 columns: 128-column slabs with the side stream on; other plans: one
  * slab, side stream on);
- * ups_plan_slab returns the current width (0 = one slab), or -1 for NULL. */
+ * ups_plan_slab returns the current width (0 = one slab), or -1 for NULL.
+ * UNSUPPORTED for a w below the column count on a plan whose column 0
+ * carries the Nyquist column (ups_plan_nyquist_packed). */
 ups_status ups_plan_set_slab(ups_plan_t plan, int columns);
 int ups_plan_slab(ups_plan_t plan);
+
+/* 1 if W's column 0 carries X[0] + i X[mx/2] (0 if not, -1 for NULL).
+ * For a real source the x transform's columns kx = 0 and kx = mx/2 are real,
+ * so one complex column holds both and the column passes run over mx/2
+ * columns, a multiple of the 128-byte line width, with no second narrow
+ * launch.  Column 0's z transforms run in a pair launch that separates the
+ * two through the Hermitian symmetry of each in (ky, kz), applies the G_hat
+ * lines of kx = 0 and mx/2 and inverts: two waves per pair of lines (ky,
+ * my - ky), beside the z pass's main launch on the plan's side stream.
+ * ups_plan_create packs FP32 plans with mx = 1024 and mz = 512 or 1024
+ * whose x and z directions are neither even nor odd (one slab); their x and
+ * z passes run the wave-per-line kernels only (ups_plan_set_kernel refuses
+ * the others with UNSUPPORTED).  Batches do not pack. */
+int ups_plan_nyquist_packed(ups_plan_t plan);
 
 /* Each column pass runs over the largest multiple of 8 x (columns per
  * 128-byte line) x-frequencies in one launch and over the remaining columns

@@ -81,6 +81,7 @@ SIGNATURES = {
     "ups_plan_set_check_finite": (C.c_int, [C.c_void_p, C.c_int]),
     "ups_plan_guard_mode": (C.c_int, [C.c_void_p]),
     "ups_plan_work_offset": (C.c_size_t, [C.c_void_p]),
+    "ups_plan_nyquist_packed": (C.c_int, [C.c_void_p]),
     "ups_batch_create": (C.c_int, [C.POINTER(ups_problem), C.c_int, C.POINTER(C.c_void_p)]),
     "ups_batch_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "ups_batch_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),

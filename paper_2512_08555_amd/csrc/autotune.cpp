@@ -122,9 +122,14 @@ const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const Plan
   const int fill = pass_fill(kind, g);
   if (!name.empty()) {
     const PassVariant* v = find_variant(kind, f64, length, name.c_str(), fill);
-    if (v) return v;
+    if (v && variant_allowed(*v, g)) return v;
   }
-  return find_variant(kind, f64, length, nullptr, fill);
+  const PassVariant* v = find_variant(kind, f64, length, nullptr, fill);
+  if (v && variant_allowed(*v, g)) return v;
+  for (const PassVariant& w : pass_variants())   // the first allowed one
+    if (w.kind == kind && w.is_f64 == (f64 ? 1 : 0) && w.length == length && w.fill == fill && variant_allowed(w, g))
+      return &w;
+  return nullptr;
 }
 
 }  // namespace ups
@@ -181,7 +186,7 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
     std::vector<const PassVariant*> cands;
     for (const PassVariant& v : pass_variants())
       if (v.kind == kKinds[k] && v.is_f64 == (g.f64 ? 1 : 0) && v.length == len[k] &&
-          v.fill == pass_fill(kKinds[k], g))
+          v.fill == pass_fill(kKinds[k], g) && variant_allowed(v, g))
         cands.push_back(&v);
     // the current choice first; a candidate replaces it only if it is faster
     // by more than the noise (1%)
@@ -207,7 +212,7 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
   // then the column schedule: one slab on one or two streams, or 128- or
   // 256-column slabs pipelined over two streams (plans with at least 256
   // columns)
-  if (err == hipSuccess && g.kx >= 256) {
+  if (err == hipSuccess && g.kx >= 256 && !g.nyq) {
     const int cur_slab = plan->slab;
     const bool cur_side = plan->use_side;
     float best_ms = 0.f;

@@ -152,6 +152,17 @@ ups_status validate_problem(const ups_problem* p, PlanGeom* g) {
   return UPS_OK;
 }
 
+bool variant_allowed(const PassVariant& v, const PlanGeom& g) {
+  if (!g.nyq) return true;
+  return !(v.kind == PASS_XFWD || v.kind == PASS_XINV || v.kind == PASS_ZCONV) || v.nch == 0;
+}
+
+void choose_nyq(PlanGeom& g) {
+  const bool mirrored_xz = g.bc[0] == UPS_BC_EVEN || g.bc[0] == UPS_BC_ODD || g.bc[2] == UPS_BC_EVEN ||
+                           g.bc[2] == UPS_BC_ODD;
+  g.nyq = !g.f64 && g.mx == 1024 && (g.mz == 512 || g.mz == 1024) && !mirrored_xz && default_slab(g) == 0;
+}
+
 void plan_layout(PlanGeom& g, bool guards) {
   const size_t ce = 2 * g.elem;  // complex element
   g.plane = (long long)g.my * g.px;
@@ -223,7 +234,8 @@ PassArgs make_args(const PlanGeom& g, const void* green) {
   a.mx = g.mx;
   a.my = g.my;
   a.mz = g.mz;
-  a.kx = g.kx;
+  a.kx = g.nyq ? g.kx - 1 : g.kx;
+  a.nyq = g.nyq ? 1 : 0;
   a.px = g.px;
   a.plane = g.plane;
   a.comp_w = g.comp_w;
@@ -320,6 +332,23 @@ hipError_t enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassAr
   const int kmain = a.kx / align * align;
   const PassVariant* nv = tail_variant(*v, a.kx - kmain);
   if (!nv || kmain == 0 || kmain == a.kx) {
+    if (a.nyq && v->kind == PASS_ZCONV) {
+      // the pair launch owns column 0: beside the main launch on the side
+      // stream (forked and joined here), else after it
+      hipError_t e = hipSuccess;
+      const bool fork = side && side->s;
+      if (fork) {
+        e = hipEventRecord(side->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+        if (e == hipSuccess) e = launch_zpair(g.f64, a, ws, side->s);
+        if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
+      }
+      if (e != hipSuccess) return e;
+      v->launch(a, ws, ws, st);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = fork ? hipStreamWaitEvent(st, side->join, 0) : launch_zpair(g.f64, a, ws, st);
+      return e;
+    }
     v->launch(a, ws, ws, st);
     return hipGetLastError();
   }
@@ -468,6 +497,7 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
   if (s != UPS_OK) return s;
   const char* gv = std::getenv("UPS_DEBUG_GUARDS");
   const bool guards = gv && *gv && std::strcmp(gv, "0") != 0;
+  choose_nyq(g);
   plan_layout(g, guards);
   const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
   const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
@@ -750,6 +780,9 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name) {
   const int len[5] = {plan->g.mx, plan->g.my, plan->g.mz, plan->g.my, plan->g.mx};
   const PassVariant* v = find_variant(kinds[pass], plan->g.f64, len[pass], name, pass_fill(kinds[pass], plan->g));
   if (!v) return fail(UPS_ERR_INVALID_ARG, "no variant '%s' for pass %d at length %d", name, pass, len[pass]);
+  if (!variant_allowed(*v, plan->g))
+    return fail(UPS_ERR_UNSUPPORTED, "'%s' cannot run pass %d of a plan whose column 0 carries the Nyquist column",
+                name, pass);
   plan->var[pass] = v;
   return ok();
 }
@@ -770,11 +803,15 @@ ups_status ups_plan_set_slab(ups_plan_t plan, int columns) {
   if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");
   if (columns < 0 || (columns > 0 && columns % 16 != 0))
     return fail(UPS_ERR_INVALID_ARG, "slab width %d is not 0 or a positive multiple of 16", columns);
+  if (plan->g.nyq && columns > 0 && columns < plan->g.kx)
+    return fail(UPS_ERR_UNSUPPORTED, "a plan whose column 0 carries the Nyquist column runs one slab");
   plan->slab = columns >= plan->g.kx ? 0 : columns;
   return ok();
 }
 
 int ups_plan_slab(ups_plan_t plan) { return plan ? plan->slab : -1; }
+
+int ups_plan_nyquist_packed(ups_plan_t plan) { return plan ? (plan->g.nyq ? 1 : 0) : -1; }
 
 ups_status ups_plan_set_side_stream(ups_plan_t plan, int enable) {
   if (!plan) return fail(UPS_ERR_INVALID_ARG, "plan is NULL");

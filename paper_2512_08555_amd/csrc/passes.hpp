@@ -4,6 +4,8 @@
 //   W[c][z][y][kx]   z < Nz, y < My, kx < Kx = Mx/2+1, row pitch px >= Kx,
 //                    plane = My * px; the x pass fills rows y < Ny, the
 //                    y-forward pass expands each plane in place to My rows.
+//                    With PassArgs::nyq, column 0 carries X[0] + i X[Mx/2]
+//                    and the passes see Kx = Mx/2 columns.
 //   Ghat[iy][kx][iz] octant iy <= My/2, iz <= Mz/2, iz fastest with pitch gz
 //                    (real T), so a z line's spectrum is contiguous.
 //   f, u             real T [c][Nz][Ny][Nx], contiguous.
@@ -33,6 +35,11 @@ struct PassArgs {
   // even (+1) or odd (-1) direction, else 0: the forward pass along that
   // axis fills rows n >= n_axis with +-(row 2 n_axis - 1 - n) instead of zeros
   int fill_x, fill_y, fill_z;
+  // 1: column 0 of W carries X[0] + i X[mx/2] (both real for a real source)
+  // and kx counts the mx/2 columns 0 .. mx/2 - 1.  The x-forward pass packs
+  // them, the x-inverse pass unpacks them, and the z pass's main launch
+  // leaves column 0 to the pair launch (launch_zpair) beside it.
+  int nyq;
 };
 
 // One problem of a grouped launch (many problems, one pass, one kernel).
@@ -76,6 +83,12 @@ struct PassVariant {
 };
 
 const std::vector<PassVariant>& pass_variants();
+// The pair launch of the z pass when a.nyq (mz = 512 or 1024): it pairs
+// the lines (ky, my - ky) of column 0, forms the products with the G_hat
+// columns kx = 0 and kx = mx/2 (2-D Hermitian symmetry of each real part),
+// inverts both and writes rows z < nz of column 0 back.  It may run beside
+// the main launch, which does not store column 0.
+hipError_t launch_zpair(bool f64, const PassArgs& a, void* W, hipStream_t st);
 // The narrowest variant of column pass v (same pass, length, precision and
 // kernel family) if it is narrower than v, else nullptr.
 const PassVariant* narrow_variant(const PassVariant& v);

@@ -49,4 +49,12 @@ std::vector<PassVariant> variants_f32_pow2() {
   };
 }
 
+hipError_t launch_zpair(bool f64, const PassArgs& a, void* W, hipStream_t st) {
+  if (f64) return hipErrorInvalidValue;   // single plans pair column 0 in FP32 only
+  if (a.mz == 1024) launch_zpair_t<float, 16>(a, W, st);
+  else if (a.mz == 512) launch_zpair_t<float, 8>(a, W, st);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace ups

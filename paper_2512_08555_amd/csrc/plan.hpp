@@ -26,6 +26,9 @@ struct PlanGeom {
   size_t green_bytes;
   size_t off_ghat, off_twx, off_twy, off_twz;
   size_t off_status;         // one status word of the debug checks (green buffer)
+  // W's column 0 carries X[0] + i X[mx/2] (single plans at mx = 1024 whose
+  // x and z passes run the wave-per-line kernels; see PassArgs::nyq)
+  bool nyq;
 };
 
 ups_status validate_problem(const ups_problem* p, PlanGeom* g);
@@ -38,6 +41,13 @@ const PassVariant* find_variant(PassKind kind, bool f64, int length, const char*
 // mirrored-fill variant, else 0
 int pass_fill(PassKind kind, const PlanGeom& g);
 const PassVariant* tuned_variant(PassKind kind, bool f64, int length, const PlanGeom& g);
+// Whether variant v may run its pass on g: with g.nyq the x passes and the
+// z pass must be wave-per-line kernels (the ones that pack, unpack and pair
+// column 0)
+bool variant_allowed(const PassVariant& v, const PlanGeom& g);
+// Decide g.nyq for a single plan (before plan_layout): FP32, mx = 1024,
+// mz = 512 or 1024, x and z neither even nor odd, one column slab
+void choose_nyq(PlanGeom& g);
 PassArgs make_args(const PlanGeom& g, const void* green);
 ups_status check_device(int* dev_out);
 ups_status set_error(ups_status s, const char* msg);

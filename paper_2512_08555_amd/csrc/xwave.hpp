@@ -71,7 +71,14 @@ __device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __res
       v[i] = ld_cx<nt_load<kNtXinvWaveBit>()>(src + (lane + 64 * (i / A) + E2 * (i % A)));
     });
     cx<T> xl = zero_c<T>();
-    if (lane == 0) xl = ld_cx<nt_load<kNtXinvWaveBit>()>(src + L);
+    if (a.nyq) {  // column 0 carries X[0] + i X[L], both real
+      if (lane == 0) {
+        xl = cx<T>{v[0].im, T(0)};
+        v[0] = cx<T>{v[0].re, T(0)};
+      }
+    } else if (lane == 0) {
+      xl = ld_cx<nt_load<kNtXinvWaveBit>()>(src + L);
+    }
     wave_fence();
     static_for<0, E>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
@@ -92,8 +99,14 @@ __device__ __forceinline__ void xwinv_body(const cx<T>* __restrict__ W, T* __res
       constexpr int i = decltype(ii)::value;
       constexpr int base = 64 * (i / A) + E2 * (i % A);
       const int k = lane + base;  // k < L, so L - k is in 1 .. L
-      const cx<T> xk = ld_cx<nt_load<4>()>(src + k);
-      const cx<T> xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
+      cx<T> xk = ld_cx<nt_load<4>()>(src + k);
+      cx<T> xm;
+      if (a.nyq && k == 0) {  // column 0 carries X[0] + i X[L], both real
+        xm = cx<T>{xk.im, T(0)};
+        xk = cx<T>{xk.re, T(0)};
+      } else {
+        xm = conj(ld_cx<nt_load<4>()>(src + (L - k)));
+      }
       v[i] = (xk + xm) + mul_i<+1>(twiddle_c<base, 2 * L, +1>(cmulc(xk - xm, wl)));
     });
   }
@@ -190,9 +203,13 @@ __device__ __forceinline__ void xwfwd_body(const T* __restrict__ f, cx<T>* __res
     const cx<T> zm = conj(zs[k == 0 ? 0 : L - k]);
     const cx<T> e = scale(zk + zm, T(0.5));
     const cx<T> o = scale(mul_i<-1>(zk - zm), T(0.5));
-    st_cx<nt_store<0>()>(dst + k, e + cmul(o, twiddle_c<base, 2 * L, -1>(wl)));
+    cx<T> xk = e + cmul(o, twiddle_c<base, 2 * L, -1>(wl));
+    // X[0] = Re Z[0] + Im Z[0], X[L] = Re Z[0] - Im Z[0] (Z[L] = Z[0],
+    // w_2L^L = -1); with nyq both go to column 0
+    if (a.nyq && k == 0) xk = cx<T>{zk.re + zk.im, zk.re - zk.im};
+    st_cx<nt_store<0>()>(dst + k, xk);
   });
-  if (lane == 0) {  // k = L: Z[L] = Z[0], w_2L^L = -1
+  if (lane == 0 && !a.nyq) {
     const cx<T> z0 = zs[0];
     st_cx<nt_store<0>()>(dst + L, cx<T>{z0.re - z0.im, T(0)});
   }

@@ -303,8 +303,10 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
 
   // ---- coalesced tile load: thread (tc, tr) moves rows tr + 64 i of column tc
   const int tc = t % CW, tr = t / CW;
-  const bool tvalid = kx0 + tc < a.kx;
-  const int tcl = tvalid ? tc : a.kx - 1 - kx0;  // in-bounds column for the loads
+  // (with a.nyq column 0 belongs to the pair launch: loaded, not stored)
+  const bool tvalid = kx0 + tc < a.kx && !(a.nyq && kx0 + tc == 0);
+  const bool tload = kx0 + tc < a.kx;
+  const int tcl = tload ? tc : a.kx - 1 - kx0;  // in-bounds column for the loads
   const unsigned toff = (unsigned(tr) * unsigned(a.plane) + unsigned(tcl)) * CB;
   cx<T>* tslot = tile + tc * CS;
   if (full) {
@@ -369,6 +371,74 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
       });
     }
   }
+}
+
+// Column 0 of a W that carries C = X0 + i XN (X0 = X[0], XN = X[mx/2],
+// each real in y and z; PassArgs::nyq).  After the y and z forward
+// transforms F_C = F_0 + i F_N with F_0 and F_N Hermitian in (ky, kz), so
+// F_0(ky, kz) = (F_C(ky, kz) + conj F_C(-ky, -kz)) / 2 and
+// F_N = (F_C - conj F_C(-ky, -kz)) / 2i.  The product the solve needs,
+// G0 F_0 + i GN F_N (G0, GN: the real G_hat lines of kx = 0 and mx/2), is
+//   R(ky, kz) = F_C(ky, kz) (G0 + GN)/2 + conj F_C(-ky, -kz) (G0 - GN)/2,
+// and its inverse is the solve's kx = 0 part plus i times its kx = mx/2
+// part.  Block b takes the lines ky = b and my - ky (once for ky = 0 and
+// my/2), one wave each: it loads rows z < nz of column 0, transforms them,
+// swaps the spectra through LDS, inverts the products and writes rows
+// z < nz of column 0 back.  It runs beside the z pass's main launch, which
+// loads column 0 with its tile but does not store it.
+template <typename T, int E>
+__global__ void __launch_bounds__(128) k_zpair(cx<T>* __restrict__ W, PassArgs a) {
+  using Z = ZWave<E>;
+  constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
+  __shared__ cx<T> spec[2][M];
+  __shared__ T xfa[2][Z::xfloats];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ky = blockIdx.x, comp = blockIdx.y;
+  const int kb = ky == 0 ? 0 : a.my - ky;
+  const bool self = kb == ky;
+  const bool active = !(self && w == 1);   // uniform over the wave
+  const int line = w ? kb : ky;
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw_z);
+  auto trow = [&](int j, int x) { return tw_row(tw, M, 1u << j)[x]; };
+  T* xf = xfa[w];
+  cx<T>* col = W + comp * a.comp_w + (long long)line * a.px;
+  cx<T> v[E];
+  if (active) {
+    static_for<0, E / 2>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int z = lane + 64 * j;
+      v[j] = z < a.nz ? col[(long long)z * a.plane] : zero_c<T>();
+    });
+    zw_forward<T, E, false>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+    static_for<0, E>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      spec[w][lane + 64 * (i / A) + E2 * (i % A)] = v[i];
+    });
+  }
+  __syncthreads();
+  if (!active) return;  // after the only barrier
+  // G_hat lines of kx = 0 and kx = mx/2 (column a.kx), iy = ky
+  const T* g0 = static_cast<const T*>(a.ghat) + (long long)ky * a.g_plane;
+  const T* gn = g0 + (long long)a.kx * a.gz;
+  const cx<T>* other = spec[self ? 0 : 1 - w];
+  static_for<0, E>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    const int k = lane + 64 * (i / A) + E2 * (i % A);
+    const int iz = k <= M - k ? k : M - k;
+    const T gp = T(0.5) * (g0[iz] + gn[iz]), gm = T(0.5) * (g0[iz] - gn[iz]);
+    v[i] = scale(v[i], gp) + scale(conj(other[(M - k) & (M - 1)]), gm);
+  });
+  zw_inverse<T, E, false>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+  static_for<0, E / 2>([&](auto ff) {
+    constexpr int f = decltype(ff)::value;
+    const int z = lane + 64 * f;
+    if (z < a.nz) col[(long long)z * a.plane] = v[f];
+  });
+}
+
+template <typename T, int E>
+void launch_zpair_t(const PassArgs& a, void* W, hipStream_t s) {
+  hipLaunchKernelGGL((k_zpair<T, E>), dim3(a.my / 2 + 1, a.ncomp), dim3(128), 0, s, static_cast<cx<T>*>(W), a);
 }
 
 // OCC: minimum waves per SIMD asked of the register allocator (1: no

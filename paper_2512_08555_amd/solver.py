@@ -154,6 +154,11 @@ class Plan:
         capi.check(capi.lib().ups_plan_set_check_finite(self._h, int(bool(enable))))
 
     @property
+    def nyquist_packed(self):
+        """Whether W's column 0 carries X[0] + i X[mx/2] (ups_plan_nyquist_packed)."""
+        return capi.lib().ups_plan_nyquist_packed(self._h) == 1
+
+    @property
     def guard_mode(self):
         """Whether the plan was created with UPS_DEBUG_GUARDS set."""
         return capi.lib().ups_plan_guard_mode(self._h) == 1
