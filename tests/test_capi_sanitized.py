@@ -1,11 +1,12 @@
 """The C-ABI host code under AddressSanitizer and UndefinedBehaviorSanitizer.
 
 `python -m paper_2512_08555_amd.build --sanitize` builds libups_san.so: the
-plan, validation, batch and autotuner sources (capi.cpp, batch.cpp,
-autotune.cpp) instrumented on the host pass only, linked with the regular
-kernel objects.  This test runs the CPU tests of the C ABI
-(test_capi_cpu.py, test_lane_offsets.py) against that library in a child
-process with the sanitizer runtime preloaded; any report aborts the child.
+plan, validation, batch, autotuner and multigrid sources (capi.cpp,
+batch.cpp, autotune.cpp, mg_capi.cpp) instrumented on the host pass only,
+linked with the regular kernel objects.  This test runs the CPU tests of the
+C ABI (test_capi_cpu.py, test_lane_offsets.py, test_mg_cpu.py,
+test_nyquist_cpu.py) against that library in a child process with the
+sanitizer runtime preloaded; any report aborts the child.
 Skipped when the sanitized library has not been built."""
 import os
 import subprocess
@@ -38,7 +39,8 @@ def test_capi_cpu_tests_under_asan_ubsan():
         "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1",
     })
     cmd = [sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-           os.path.join(ROOT, "tests", "test_capi_cpu.py"), os.path.join(ROOT, "tests", "test_lane_offsets.py")]
+           os.path.join(ROOT, "tests", "test_capi_cpu.py"), os.path.join(ROOT, "tests", "test_lane_offsets.py"),
+           os.path.join(ROOT, "tests", "test_mg_cpu.py"), os.path.join(ROOT, "tests", "test_nyquist_cpu.py")]
     r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600, cwd=ROOT)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
