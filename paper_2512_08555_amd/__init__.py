@@ -10,11 +10,11 @@ The HIP library is loaded on first use; importing the package alone (for
 built.
 """
 
-__all__ = ["Plan", "Batch", "solve", "PoissonSolve", "poisson_solve", "supported_length", "auto_pad"]
+__all__ = ["Plan", "Batch", "Multigrid", "solve", "PoissonSolve", "poisson_solve", "supported_length", "auto_pad"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "Batch", "solve"):
+    if name in ("Plan", "Batch", "Multigrid", "solve"):
         from . import solver
         return getattr(solver, name)
     if name in ("PoissonSolve", "poisson_solve"):
