@@ -161,3 +161,29 @@ def test_second_order_on_a_gaussian_with_two_boxes():
         assert max(res) < 1e-9 * float(fd[0].abs().max())
     p = np.log2(errs[0] / errs[1])
     assert 1.85 < p < 2.3, (errs, p)
+
+
+def test_cycle_with_a_periodic_coarse_plan():
+    # level 0 periodic along z and unbounded in x and y (eq. 2unbkernel):
+    # the boxes sit strictly inside level 0, so the cycle is unchanged and
+    # only the direct solve on level 0 differs
+    from oracle import bc as obc
+    n0, patches = (16, 13, 14), [((4, 3, 3), (6, 5, 6))]
+    bc = ("per", "unb", "unb")
+    rng = np.random.default_rng(50)
+    shapes = omg.level_shapes(n0, patches)
+    fs = [rng.standard_normal(s) for s in shapes]
+    pad = (32,) + tuple(auto_pad(n0, "f64")[1:])
+    plan = Plan(n0, H0, "f64", pad=pad, bc=bc)
+    mg = Multigrid(plan, patches)
+    print("[case] multigrid, periodic z coarse plan %s pad %s" % (n0, pad), flush=True)
+    fd = [torch.from_numpy(f).cuda() for f in fs]
+    ud = mg.zeros()
+    us = [np.zeros(s) for s in shapes]
+    coarse = lambda f, h: obc.solve_bc(f, h, bc, M=pad)
+    for _ in range(3):
+        mg.cycle(fd, ud, 2, 2)
+        omg.vcycle(us, fs, patches, H0, 2, 2, coarse_solve=coarse)
+    err = _compare(ud, us)
+    print("  rel err %.2e" % err, flush=True)
+    assert err < 1e-12
