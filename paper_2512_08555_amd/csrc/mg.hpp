@@ -22,13 +22,11 @@ struct MgBox {
 // footprint of box b on every side
 hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp, MgBox b, hipStream_t st);
 
-// one red-black half-step: every unknown of colour `color` ((x + y + z) % 2)
-// set to (sum of its six neighbours - h^2 f) / 6
-hipError_t mg_smooth(bool f64, void* u, const void* f, MgGrid g, double h, int color, hipStream_t st);
-
-// nu red-black iterations on u, the same values as 2 nu half-steps: an odd
-// first one as two half-steps in place, then pairs of whole iterations
-// u -> s -> u by the fused kernel (s: a scratch array of the level's size)
+// nu red-black iterations on u, the same values as 2 nu half-steps (red:
+// every unknown with (x + y + z) even set to (sum of its six neighbours -
+// h^2 f) / 6, then black): whole iterations by the fused kernel, u -> s ->
+// u ..., and a copy back into u after an odd count (s: a scratch array of
+// the level's size)
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
                                 hipStream_t st);
 

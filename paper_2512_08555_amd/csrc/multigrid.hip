@@ -117,154 +117,231 @@ __global__ void __launch_bounds__(256) k_mg_ghosts(T* __restrict__ u, MgGrid g, 
   u[lin(x, y, z, g)] = interp_cubic(up, gp, b, x, y, z);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBX * kBY) k_mg_rbgs(T* __restrict__ u, const T* __restrict__ f, MgGrid g, T h2,
-                                                       int color) {
-  const int z = blockIdx.z + 1;
-  const int y = blockIdx.y * kBY + threadIdx.y + 1;
-  if (y > g.ny - 2) return;
-  const int p = (color + y + z) & 1;           // parity of x for this colour
-  const int x = (2 - p) + 2 * int(blockIdx.x * kBX + threadIdx.x);
-  if (x > g.nx - 2) return;
-  const size_t sy = g.nx, sz = (size_t)g.nx * g.ny;
-  const size_t i = lin(x, y, z, g);
-  const T nb = u[i + sz] + u[i - sz] + u[i + sy] + u[i - sy] + u[i + 1] + u[i - 1];
-  u[i] = (nb - h2 * f[i]) / T(6);
-}
-
 // One whole red-black iteration from uin into uout (two different arrays),
-// the same arithmetic as a red half-step followed by a black one.  A block
-// owns a tile of 64 (x) by TY (y) nodes and a chunk of kZC planes, and
-// marches up z with rings of planes in LDS: u_in with a halo of 2, the
-// half-updated values H (red unknowns new, every other node as in u_in)
-// with a halo of 1, and f.  H of plane p is computed on the tile and its
-// halo from u_in (the halo's red values again, so no block reads what
-// another writes); the black unknowns of plane p - 1 then follow from H of
-// planes p - 2 .. p.  Every node of the tile, ghost layer included, is
-// written to uout.  The chunk starts two planes early to fill the rings,
-// and the next plane's loads are in flight while the current one is
-// updated.
+// the same arithmetic as a red half-step followed by a black one.
+//
+// Tiles start at node 1: a block owns TX x TY columns (x0 .. x0 + TX - 1,
+// y0 .. y0 + TY - 1, x0 and y0 = 1 mod TX and TY) and a chunk of kZC
+// planes from zs = 1 mod kZC, and marches up z.  Levels of 2^k + 1 nodes
+// then split into whole tiles; the ghost nodes at index 0 belong to no tile
+// and are written through by the blocks next to them.
+//
+// Each thread owns TX TY / NT interior columns and up to NR columns of the
+// frame of width 2 around the tile, and keeps their values of u_in (planes
+// p - 1 .. p + 2) and f in a ring of four register slots: the loop is
+// unrolled by four so that slot indices are compile-time constants and no
+// register copy waits on a load in flight.  Step p:
+//   - u_in of plane p goes to LDS (halo 2), then one barrier;
+//   - red of plane p on the tile and its halo of 1 (the halo's values again,
+//     so that no block reads what another writes) from the LDS plane and the
+//     column's own z neighbours; H (red new, black as in u_in) to LDS;
+//   - black of plane p - 1 on the tile from the H plane written one step
+//     earlier and the column's own H of planes p - 2 and p, then the store;
+//   - loads of plane p + 3 into the slot of plane p - 1.
+// The LDS planes of u_in and H are double-buffered, which is what makes one
+// barrier per step enough.  Loads use clamped addresses: a value outside the
+// level only ever feeds a stencil whose result is discarded.  Addresses are a
+// wave-uniform plane base plus a 32-bit byte offset in the plane: the cycle
+// smooths refined levels only, which hold at most 2^31 - 1 nodes in at least
+// 5 planes, so a plane stays below 2^32 bytes in FP64.
 constexpr int kZC = 32;
 
-template <typename T, int TY>
-__global__ void __launch_bounds__(256) k_mg_gs2(const T* __restrict__ uin, T* __restrict__ uout,
-                                                const T* __restrict__ f, MgGrid g, T h2) {
-  constexpr int TX = 64;
-  constexpr int UX = TX + 4, UY = TY + 4;
-  constexpr int HX = TX + 2, HY = TY + 2;
-  constexpr int NU = (UX * UY + 255) / 256;   // u_in values each thread stages per plane
-  constexpr int NH = (HX * HY + 255) / 256;   // f and H values per thread
-  constexpr int NB = TX * TY / 256;           // outputs per thread
-  __shared__ T U[3][UY][UX];
-  __shared__ T H[3][HY][HX];
-  __shared__ T F[3][HY][HX];   // three slots: f of p + 1 is staged while black reads f of p - 1
-  // XCD-aware tile order: blocks are dealt to the 8 XCDs in turn, so block
-  // b runs on XCD b % 8; each XCD takes one contiguous run of tiles ordered
-  // y fastest, then x, then z chunk, and tiles that share halo rows run on
-  // the same XCD (its L2) at about the same time.
-  const int nty = (g.ny + TY - 1) / TY, ntx = (g.nx + TX - 1) / TX;
-  const int ntiles = nty * ntx * ((g.nz + kZC - 1) / kZC);
+template <int K>
+struct Slot {
+  static constexpr int value = K;
+};
+
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_mg_gs2(const T* __restrict__ uin, T* __restrict__ uout,
+                                               const T* __restrict__ f, MgGrid g, T h2) {
+  constexpr int UX = TX + 4, UY = TY + 4, HX = TX + 2, HY = TY + 2;
+  static_assert((TX * TY) % NT == 0, "interior columns split evenly over the threads");
+  constexpr int NI = TX * TY / NT;          // interior columns per thread
+  constexpr int NRING = 4 * UX + 4 * TY;    // frame of width 2
+  constexpr int NR = (NRING + NT - 1) / NT;
+  __shared__ T Us[2][UY][UX];
+  __shared__ T Hs[2][HY][HX];
+  // XCD-aware tile order: block b runs on XCD b % 8, and each XCD takes one
+  // contiguous run of tiles ordered y fastest, then x, then z chunk, so that
+  // tiles sharing halo rows run on the same XCD (its L2) at about the same time
+  const int nty = (g.ny - 1 + TY - 1) / TY, ntx = (g.nx - 1 + TX - 1) / TX;
+  const int ntiles = nty * ntx * ((g.nz - 1 + kZC - 1) / kZC);
   const int per_xcd = (ntiles + 7) / 8;
   const int unit = int(blockIdx.x % 8) * per_xcd + int(blockIdx.x / 8);
   if (unit >= ntiles) return;
   const int tyi = unit % nty, txi = (unit / nty) % ntx, tzi = unit / (nty * ntx);
-  const int tid = threadIdx.y * kBX + threadIdx.x;
-  const int x0 = txi * TX, y0 = tyi * TY;
-  const int zs = tzi * kZC, ze = min(zs + kZC, g.nz);
-  const size_t sy = g.nx, sz = (size_t)g.nx * g.ny;
-  auto in_grid = [&](int x, int y, int z) {
-    return z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
+  const int x0 = 1 + txi * TX, y0 = 1 + tyi * TY;
+  const int zs = 1 + tzi * kZC, ze = min(zs + kZC, g.nz);
+  const int t = threadIdx.x;
+  const size_t sz = (size_t)g.nx * g.ny;
+  auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  // byte offset of column (x, y) in a plane, clamped into the level
+  auto col_off = [&](int x, int y) {
+    return unsigned(clampi(y, 0, g.ny - 1) * g.nx + clampi(x, 0, g.nx - 1)) * unsigned(sizeof(T));
+  };
+  int ilx[NI], ily[NI];   // interior columns, in LDS coordinates (halo 2)
+  unsigned ioff[NI];
+  bool iok[NI];
+#pragma unroll
+  for (int s = 0; s < NI; ++s) {
+    const int e = t + NT * s;
+    ilx[s] = 2 + e % TX;
+    ily[s] = 2 + e / TX;
+    const int x = x0 - 2 + ilx[s], y = y0 - 2 + ily[s];
+    iok[s] = x < g.nx && y < g.ny;
+    ioff[s] = col_off(x, y);
+  }
+  // frame columns r: rows 0, 1 and UY - 2, UY - 1 whole, then columns 0, 1,
+  // UX - 2, UX - 1 of rows 2 .. TY + 1
+  int rlx[NR], rly[NR];
+  unsigned roff[NR], rfoff[NR];
+  bool rval[NR], rin[NR], rgh[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int r = t + NT * s;
+    int lx, ly;
+    if (r < 2 * UX) {
+      ly = r / UX;
+      lx = r - ly * UX;
+    } else if (r < 4 * UX) {
+      const int r2 = r - 2 * UX;
+      ly = UY - 2 + r2 / UX;
+      lx = r2 % UX;
+    } else {
+      const int r3 = r - 4 * UX, c = r3 & 3;
+      ly = 2 + (r3 >> 2);
+      lx = c < 2 ? c : UX - 4 + c;
+    }
+    rval[s] = r < NRING;
+    if (!rval[s]) lx = ly = 2;
+    rlx[s] = lx;
+    rly[s] = ly;
+    const int x = x0 - 2 + lx, y = y0 - 2 + ly;
+    rin[s] = rval[s] && lx >= 1 && ly >= 1 && lx <= UX - 2 && ly <= UY - 2;   // in the halo of 1
+    rgh[s] = rval[s] && x >= 0 && y >= 0 && x < g.nx && y < g.ny &&
+             ((x == 0 && (y >= y0 || y == 0) && y < y0 + TY) || (y == 0 && x >= x0 && x < x0 + TX));
+    roff[s] = col_off(x, y);
+    // f is needed on the halo of 1 only: outer columns load their nearest
+    // such column's value (the same cache line)
+    rfoff[s] = col_off(x0 - 2 + clampi(lx, 1, UX - 2), y0 - 2 + clampi(ly, 1, UY - 2));
+  }
+  auto ld = [&](const T* a, unsigned off, int p) -> T {
+    const char* base = reinterpret_cast<const char*>(a + (size_t)clampi(p, 0, g.nz - 1) * sz);
+    return *reinterpret_cast<const T*>(base + off);
+  };
+  auto st = [&](int p, unsigned off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(uout + (size_t)p * sz) + off) = v;
   };
   auto unknown = [&](int x, int y, int z) {
     return z >= 1 && z <= g.nz - 2 && y >= 1 && y <= g.ny - 2 && x >= 1 && x <= g.nx - 2;
   };
-  // plane p of u_in (halo 2) and of f (halo 1) into registers; the loads
-  // are issued here and waited for only when the registers go to LDS
-  T ru[NU], rf[NH];
-  auto fetch = [&](int pu, int pf) {
+  // ring slots: plane p lives in slot (p - p0) & 3
+  T iu[4][NI], iF[4][NI], ih[4][NI], ru[4][NR], rF[4][NR];
+  const int p0 = zs - 1;
 #pragma unroll
-    for (int t = 0; t < NU; ++t) {
-      const int e = tid + 256 * t;
-      const int ly = e / UX, lx = e - ly * UX;
-      const int x = x0 - 2 + lx, y = y0 - 2 + ly;
-      ru[t] = (e < UX * UY && in_grid(x, y, pu)) ? uin[(size_t)pu * sz + (size_t)y * sy + x] : T(0);
-    }
+  for (int s = 0; s < NI; ++s) {
+    iu[3][s] = ld(uin, ioff[s], p0 - 1);
+    iu[0][s] = ld(uin, ioff[s], p0);
+    iu[1][s] = ld(uin, ioff[s], p0 + 1);
+    iu[2][s] = ld(uin, ioff[s], p0 + 2);
+    iF[0][s] = ld(f, ioff[s], p0);
+    iF[1][s] = ld(f, ioff[s], p0 + 1);
+    iF[2][s] = ld(f, ioff[s], p0 + 2);
+    iF[3][s] = T(0);
+    ih[0][s] = ih[1][s] = ih[2][s] = ih[3][s] = T(0);
+  }
 #pragma unroll
-    for (int t = 0; t < NH; ++t) {
-      const int e = tid + 256 * t;
-      const int ly = e / HX, lx = e - ly * HX;
-      const int x = x0 - 1 + lx, y = y0 - 1 + ly;
-      rf[t] = (e < HX * HY && in_grid(x, y, pf)) ? f[(size_t)pf * sz + (size_t)y * sy + x] : T(0);
-    }
-  };
-  auto stage = [&](int pu, int pf) {
-    T(*du)[UX] = U[(pu + 6) % 3];
+  for (int s = 0; s < NR; ++s) {
+    ru[3][s] = ld(uin, roff[s], p0 - 1);
+    ru[0][s] = ld(uin, roff[s], p0);
+    ru[1][s] = ld(uin, roff[s], p0 + 1);
+    ru[2][s] = ld(uin, roff[s], p0 + 2);
+    rF[0][s] = ld(f, rfoff[s], p0);
+    rF[1][s] = ld(f, rfoff[s], p0 + 1);
+    rF[2][s] = ld(f, rfoff[s], p0 + 2);
+    rF[3][s] = T(0);
+  }
+  auto step = [&](auto slot, int p) {
+    constexpr int k = decltype(slot)::value;   // plane p
+    constexpr int km = (k + 3) & 3, kp = (k + 1) & 3, kmm = (k + 2) & 3;   // p - 1, p + 1, p - 2
+    T(*U)[UX] = Us[p & 1];
+    T(*Hw)[HX] = Hs[p & 1];
 #pragma unroll
-    for (int t = 0; t < NU; ++t) {
-      const int e = tid + 256 * t;
-      if (e < UX * UY) du[e / UX][e % UX] = ru[t];
-    }
-    T(*df)[HX] = F[(pf + 6) % 3];
+    for (int s = 0; s < NI; ++s) U[ily[s]][ilx[s]] = iu[k][s];
 #pragma unroll
-    for (int t = 0; t < NH; ++t) {
-      const int e = tid + 256 * t;
-      if (e < HX * HY) df[e / HX][e % HX] = rf[t];
-    }
-  };
-  auto red = [&](int p) {
-    const T(*Um)[UX] = U[(p + 5) % 3];
-    const T(*U0)[UX] = U[(p + 6) % 3];
-    const T(*Up)[UX] = U[(p + 7) % 3];
-    const T(*Fp)[HX] = F[(p + 6) % 3];
-    T(*Hd)[HX] = H[(p + 6) % 3];
+    for (int s = 0; s < NR; ++s)
+      if (rval[s]) U[rly[s]][rlx[s]] = ru[k][s];
+    __syncthreads();
+    // red of plane p on the tile and its halo
 #pragma unroll
-    for (int t = 0; t < NH; ++t) {
-      const int e = tid + 256 * t;
-      if (e >= HX * HY) break;
-      const int ly = e / HX, lx = e - ly * HX;
-      const int x = x0 - 1 + lx, y = y0 - 1 + ly;
-      const int ux = lx + 1, uy = ly + 1;
-      T v = U0[uy][ux];
+    for (int s = 0; s < NI; ++s) {
+      const int lx = ilx[s], ly = ily[s], x = x0 - 2 + lx, y = y0 - 2 + ly;
+      T v = iu[k][s];
       if (unknown(x, y, p) && ((x + y + p) & 1) == 0) {
-        const T nb = Up[uy][ux] + Um[uy][ux] + U0[uy + 1][ux] + U0[uy - 1][ux] + U0[uy][ux + 1] + U0[uy][ux - 1];
-        v = (nb - h2 * Fp[ly][lx]) / T(6);
+        const T nb = iu[kp][s] + iu[km][s] + U[ly + 1][lx] + U[ly - 1][lx] + U[ly][lx + 1] + U[ly][lx - 1];
+        v = (nb - h2 * iF[k][s]) / T(6);
       }
-      Hd[ly][lx] = v;
+      ih[k][s] = v;
+      Hw[ly - 1][lx - 1] = v;
     }
-  };
-  auto black = [&](int q) {
-    const T(*Hm)[HX] = H[(q + 5) % 3];
-    const T(*H0)[HX] = H[(q + 6) % 3];
-    const T(*Hp)[HX] = H[(q + 7) % 3];
-    const T(*Fq)[HX] = F[(q + 6) % 3];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      const int e = tid + 256 * t;
-      const int ly = e / TX, lx = e - ly * TX;
-      const int x = x0 + lx, y = y0 + ly;
-      if (x >= g.nx || y >= g.ny) continue;
-      const int hx = lx + 1, hy = ly + 1;
-      T v = H0[hy][hx];
-      if (unknown(x, y, q) && ((x + y + q) & 1) == 1) {
-        const T nb = Hp[hy][hx] + Hm[hy][hx] + H0[hy + 1][hx] + H0[hy - 1][hx] + H0[hy][hx + 1] + H0[hy][hx - 1];
-        v = (nb - h2 * Fq[hy][hx]) / T(6);
+    for (int s = 0; s < NR; ++s) {
+      if (!rin[s]) continue;
+      const int lx = rlx[s], ly = rly[s], x = x0 - 2 + lx, y = y0 - 2 + ly;
+      T v = ru[k][s];
+      if (unknown(x, y, p) && ((x + y + p) & 1) == 0) {
+        const T nb = ru[kp][s] + ru[km][s] + U[ly + 1][lx] + U[ly - 1][lx] + U[ly][lx + 1] + U[ly][lx - 1];
+        v = (nb - h2 * rF[k][s]) / T(6);
       }
-      uout[(size_t)q * sz + (size_t)y * sy + x] = v;
+      Hw[ly - 1][lx - 1] = v;
+    }
+    if (p == 0) {   // the ghost plane z = 0, ahead of the first chunk
+#pragma unroll
+      for (int s = 0; s < NI; ++s)
+        if (iok[s]) st(0, ioff[s], iu[k][s]);
+#pragma unroll
+      for (int s = 0; s < NR; ++s)
+        if (rgh[s]) st(0, roff[s], ru[k][s]);
+    }
+    // black of plane q = p - 1 on the tile
+    const int q = p - 1;
+    if (q >= zs) {
+#pragma unroll
+      for (int s = 0; s < NR; ++s)
+        if (rgh[s]) st(q, roff[s], ru[km][s]);
+      const T(*Hq)[HX] = Hs[q & 1];
+#pragma unroll
+      for (int s = 0; s < NI; ++s) {
+        if (!iok[s]) continue;
+        const int hx = ilx[s] - 1, hy = ily[s] - 1, x = x0 - 2 + ilx[s], y = y0 - 2 + ily[s];
+        T v = ih[km][s];
+        if (unknown(x, y, q) && ((x + y + q) & 1) == 1) {
+          const T nb = ih[k][s] + ih[kmm][s] + Hq[hy + 1][hx] + Hq[hy - 1][hx] + Hq[hy][hx + 1] + Hq[hy][hx - 1];
+          v = (nb - h2 * iF[km][s]) / T(6);
+        }
+        st(q, ioff[s], v);
+      }
+    }
+    // plane p + 3 into the slot of plane p - 1
+#pragma unroll
+    for (int s = 0; s < NI; ++s) {
+      iu[km][s] = ld(uin, ioff[s], p + 3);
+      iF[km][s] = ld(f, ioff[s], p + 3);
+    }
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      ru[km][s] = ld(uin, roff[s], p + 3);
+      rF[km][s] = ld(f, rfoff[s], p + 3);
     }
   };
-  // prologue: u_in planes zs - 2 and zs - 1 staged, zs and f of zs - 1 in flight
-  fetch(zs - 2, zs - 1);
-  stage(zs - 2, zs - 1);
-  fetch(zs - 1, zs - 1);
-  stage(zs - 1, zs - 1);
-  fetch(zs, zs - 1);
-  for (int p = zs - 1; p <= ze; ++p) {
-    stage(p + 1, p);          // u_in of p + 1, f of p
-    fetch(p + 2, p + 1);      // in flight during the updates below
-    __syncthreads();
-    red(p);
-    __syncthreads();
-    if (p - 1 >= zs) black(p - 1);
+  for (int p = p0; p <= ze; p += 4) {
+    step(Slot<0>(), p);
+    if (p + 1 > ze) break;
+    step(Slot<1>(), p + 1);
+    if (p + 2 > ze) break;
+    step(Slot<2>(), p + 2);
+    if (p + 3 > ze) break;
+    step(Slot<3>(), p + 3);
   }
 }
 
@@ -432,43 +509,61 @@ hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp
   return hipGetLastError();
 }
 
-hipError_t mg_smooth(bool f64, void* u, const void* f, MgGrid g, double h, int color, hipStream_t st) {
-  const int nxc = (g.nx - 1) / 2;             // unknowns of one colour per row, at most
-  const dim3 grid = grid_xyz(nxc, g.ny - 2, g.nz - 2), block(kBX, kBY);
-  if (f64)
-    hipLaunchKernelGGL(k_mg_rbgs<double>, grid, block, 0, st, static_cast<double*>(u), static_cast<const double*>(f),
-                       g, h * h, color);
-  else
-    hipLaunchKernelGGL(k_mg_rbgs<float>, grid, block, 0, st, static_cast<float*>(u), static_cast<const float*>(f), g,
-                       float(h * h), color);
+namespace {
+
+// Tile shapes of the fused iteration (x width, y height, threads), widest
+// first; a level takes the first one whose tiles pad its nx - 1 columns
+// least.  Measured at 513^3: 256 x 8 (FP32) and 128 x 16 (FP64) are the
+// fastest shapes that split the level into whole tiles.
+struct GsShape {
+  int tx, ty, nt;
+};
+constexpr GsShape kGs32[] = {{256, 8, 1024}, {128, 16, 1024}, {64, 16, 512}};
+constexpr GsShape kGs64[] = {{128, 16, 1024}, {64, 16, 512}};
+
+int gs_shape(const GsShape* c, int n, int nx) {
+  auto padded = [&](int i) { return (nx - 1 + c[i].tx - 1) / c[i].tx * c[i].tx; };
+  int best = 0;
+  for (int i = 1; i < n; ++i)
+    if (padded(i) < padded(best)) best = i;
+  return best;
+}
+
+template <typename T, int TX, int TY, int NT>
+hipError_t launch_gs2(const void* a, void* b, const void* f, MgGrid g, double h, hipStream_t st) {
+  const long long ntiles =
+      (long long)((g.nx - 1 + TX - 1) / TX) * ((g.ny - 1 + TY - 1) / TY) * ((g.nz - 1 + kZC - 1) / kZC);
+  hipLaunchKernelGGL((k_mg_gs2<T, TX, TY, NT>), dim3(unsigned(8 * ((ntiles + 7) / 8))), dim3(NT), 0, st,
+                     static_cast<const T*>(a), static_cast<T*>(b), static_cast<const T*>(f), g, T(h * h));
   return hipGetLastError();
 }
 
+hipError_t smooth_fused(bool f64, const void* a, void* b, const void* f, MgGrid g, double h, hipStream_t st) {
+  static_assert(kGs64[0].tx == 128 && kGs64[1].tx == 64, "launch table below");
+  static_assert(kGs32[0].tx == 256 && kGs32[1].tx == 128 && kGs32[2].tx == 64, "launch table below");
+  if (f64)
+    return gs_shape(kGs64, 2, g.nx) == 0 ? launch_gs2<double, 128, 16, 1024>(a, b, f, g, h, st)
+                                          : launch_gs2<double, 64, 16, 512>(a, b, f, g, h, st);
+  switch (gs_shape(kGs32, 3, g.nx)) {
+    case 0: return launch_gs2<float, 256, 8, 1024>(a, b, f, g, h, st);
+    case 1: return launch_gs2<float, 128, 16, 1024>(a, b, f, g, h, st);
+    default: return launch_gs2<float, 64, 16, 512>(a, b, f, g, h, st);
+  }
+}
+
+}  // namespace
+
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
                                 hipStream_t st) {
+  // nu fused iterations, alternately u -> s and s -> u; after an odd count
+  // the result is in s and is copied back (2 arrays of traffic, against the 3
+  // of an iteration split into two in-place half-steps)
   hipError_t e = hipSuccess;
-  if (nu & 1) {
-    e = mg_smooth(f64, u, f, g, h, 0, st);
-    if (e == hipSuccess) e = mg_smooth(f64, u, f, g, h, 1, st);
-  }
-  constexpr int TY64 = 8, TY32 = 8;
-  const int ty = f64 ? TY64 : TY32;
-  const long long ntiles = (long long)((g.nx + 63) / 64) * ((g.ny + ty - 1) / ty) * ((g.nz + kZC - 1) / kZC);
-  const dim3 grid(unsigned(8 * ((ntiles + 7) / 8)));
-  const dim3 block(kBX, kBY);
-  for (int it = 0; it < nu / 2 && e == hipSuccess; ++it) {
-    for (int half = 0; half < 2 && e == hipSuccess; ++half) {
-      const void* a = half ? s : u;
-      void* b = half ? u : s;
-      if (f64)
-        hipLaunchKernelGGL((k_mg_gs2<double, TY64>), grid, block, 0, st, static_cast<const double*>(a),
-                           static_cast<double*>(b), static_cast<const double*>(f), g, h * h);
-      else
-        hipLaunchKernelGGL((k_mg_gs2<float, TY32>), grid, block, 0, st, static_cast<const float*>(a),
-                           static_cast<float*>(b), static_cast<const float*>(f), g, float(h * h));
-      e = hipGetLastError();
-    }
-  }
+  for (int it = 0; it < nu && e == hipSuccess; ++it)
+    e = (it & 1) ? smooth_fused(f64, s, u, f, g, h, st) : smooth_fused(f64, u, s, f, g, h, st);
+  if (e == hipSuccess && (nu & 1))
+    e = hipMemcpyAsync(u, s, (size_t)g.nx * g.ny * g.nz * (f64 ? sizeof(double) : sizeof(float)),
+                       hipMemcpyDeviceToDevice, st);
   return e;
 }
 

@@ -97,28 +97,6 @@ def _levels(n0, patches):
 
 
 @pytest.mark.parametrize("n0,patches", HIERARCHIES)
-def test_smoothing_covers_each_unknown_of_its_colour_once(n0, patches):
-    for nz, ny, nx in _levels(n0, patches):
-        for color in (0, 1):
-            nxc = (nx - 1) // 2
-            bx, by, bz, tx, ty = _threads(_grid(nxc, ny - 2, nz - 2), (BX, BY))
-            z = bz + 1
-            y = by * BY + ty + 1
-            ok = y <= ny - 2
-            p = (color + y + z) & 1
-            x = (2 - p) + 2 * (bx * BX + tx)
-            ok &= x <= nx - 2
-            x, y, z = x[ok], y[ok], z[ok]
-            assert x.min() >= 1 and y.min() >= 1 and z.min() >= 1
-            hit = np.zeros((nz, ny, nx), int)
-            np.add.at(hit, (z, y, x), 1)
-            zz, yy, xx = np.indices((nz, ny, nx))
-            want = ((xx + yy + zz) % 2 == color) & (xx > 0) & (yy > 0) & (zz > 0) & (xx < nx - 1) & \
-                   (yy < ny - 1) & (zz < nz - 1)
-            assert np.array_equal(hit, want.astype(int))
-
-
-@pytest.mark.parametrize("n0,patches", HIERARCHIES)
 def test_ghost_kernel_covers_the_ghost_layer_once(n0, patches):
     for nz, ny, nx in _levels(n0, patches)[1:]:
         plane, ring = nx * ny, 2 * nx + 2 * (ny - 2)
@@ -245,32 +223,109 @@ def test_residual_norm_rows_cover_the_unknowns_once(n0, patches):
         assert np.array_equal(seen, want)
 
 
-@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), [])])
-@pytest.mark.parametrize("ty", [8, 16])
-def test_fused_smoothing_tiles_cover_the_level_once(n0, patches, ty):
-    # the fused red-black iteration: tiles of 64 x TY nodes by chunks of 32
-    # planes write every node once; the LDS regions (u_in with a halo of 2,
-    # H and f with a halo of 1) hold every neighbour the updates read
-    TX, ZC = 64, 32
-    UX, UY, HX, HY = TX + 4, ty + 4, TX + 2, ty + 2
+# tile shapes of the fused red-black iteration (x width, y height, threads)
+GS32 = [(256, 8, 1024), (128, 16, 1024), (64, 16, 512)]
+GS64 = [(128, 16, 1024), (64, 16, 512)]
+GS_ZC = 32
+
+
+def _gs_shape(prec, nx):
+    # the first shape whose tiles pad the nx - 1 columns from node 1 least
+    shapes = GS64 if prec == "f64" else GS32
+    padded = [(nx - 2 + tx) // tx * tx for tx, _, _ in shapes]
+    return shapes[padded.index(min(padded))]
+
+
+def test_fused_smoothing_shape_choice():
+    assert _gs_shape("f32", 513) == (256, 8, 1024)
+    assert _gs_shape("f32", 257) == (256, 8, 1024)
+    assert _gs_shape("f32", 385) == (128, 16, 1024)
+    assert _gs_shape("f32", 301) == (64, 16, 512)
+    assert _gs_shape("f32", 13) == (64, 16, 512)
+    assert _gs_shape("f64", 513) == (128, 16, 1024)
+    assert _gs_shape("f64", 301) == (64, 16, 512)
+
+
+def _gs_frame(tx, ty):
+    """Frame columns (lx, ly) of width 2 around a tx x ty tile, in the
+    order the kernel numbers them (LDS coordinates, halo 2)."""
+    ux, uy = tx + 4, ty + 4
+    out = []
+    for r in range(4 * ux + 4 * ty):
+        if r < 2 * ux:
+            ly, lx = r // ux, r % ux
+        elif r < 4 * ux:
+            ly, lx = uy - 2 + (r - 2 * ux) // ux, (r - 2 * ux) % ux
+        else:
+            r3 = r - 4 * ux
+            c = r3 & 3
+            ly, lx = 2 + (r3 >> 2), (c if c < 2 else ux - 4 + c)
+        out.append((lx, ly))
+    return out
+
+
+@pytest.mark.parametrize("shape", GS32 + GS64[1:])
+def test_fused_smoothing_frame_and_lds(shape):
+    tx, ty, nt = shape
+    ux, uy, hx, hy = tx + 4, ty + 4, tx + 2, ty + 2
+    assert tx * ty % nt == 0
+    frame = _gs_frame(tx, ty)
+    assert len(set(frame)) == len(frame)
+    inner = {(2 + e % tx, 2 + e // tx) for e in range(tx * ty)}
+    assert inner.isdisjoint(frame) and len(inner) + len(frame) == ux * uy
+    # red runs on the halo of 1 (interior plus the frame's inner ring), reads
+    # U at +-1 and writes H at (lx - 1, ly - 1); black reads H at +-1
+    red = inner | {(lx, ly) for lx, ly in frame if 1 <= lx <= ux - 2 and 1 <= ly <= uy - 2}
+    assert len(red) == hx * hy
+    for lx, ly in red:
+        assert 0 <= lx - 1 and lx + 1 <= ux - 1 and 0 <= ly - 1 and ly + 1 <= uy - 1
+        assert 0 <= lx - 1 < hx and 0 <= ly - 1 < hy
+    for lx, ly in inner:
+        # H index (lx - 1, ly - 1) and its four neighbours
+        assert 0 <= lx - 2 and lx <= hx - 1 and 0 <= ly - 2 and ly <= hy - 1
+    # f of an outer frame column is read at its nearest halo-1 column
+    for lx, ly in frame:
+        assert (min(max(lx, 1), ux - 2), min(max(ly, 1), uy - 2)) in red
+    # four register slots: plane p in (p - p0) & 3; a step reads p - 2 .. p + 1
+    # and loads p + 3 into the slot of p - 1 after its last use
+    for k in range(4):
+        assert (k + 3) % 4 == (k - 1) % 4 and (k + 2) % 4 == (k - 2) % 4
+        assert len({k, (k + 1) % 4, (k + 3) % 4, (k + 2) % 4}) == 4
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), []), ((33, 65, 513), [])])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_smoothing_writes_every_node_once(n0, patches, prec):
+    # tiles from node 1 by chunks of 32 planes from plane 1 (the XCD-aware
+    # block order), the ghost faces at index 0 through the frame and the
+    # first chunk: every node of the level is written exactly once, and the
+    # loads (clamped) and stores stay in the level
     for nz, ny, nx in _levels(n0, patches):
+        tx, ty, nt = _gs_shape(prec, nx)
         hit = np.zeros((nz, ny, nx), int)
-        nty, ntx = (ny + ty - 1) // ty, (nx + TX - 1) // TX
-        ntiles = nty * ntx * ((nz + ZC - 1) // ZC)
+        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
+        ntiles = nty * ntx * ((nz - 2 + GS_ZC) // GS_ZC)
         per_xcd = (ntiles + 7) // 8
-        for b in range(8 * per_xcd):          # the launch: 8 per_xcd blocks
+        frame = np.array(_gs_frame(tx, ty))
+        units = []
+        for b in range(8 * per_xcd):
             unit = (b % 8) * per_xcd + b // 8
-            if unit >= ntiles:
-                continue
+            if unit < ntiles:
+                units.append(unit)
+        assert sorted(units) == list(range(ntiles))
+        for unit in units:
             tyi, txi, tzi = unit % nty, (unit // nty) % ntx, unit // (nty * ntx)
-            zs, ze = tzi * ZC, min(tzi * ZC + ZC, nz)
-            x = txi * TX + np.arange(TX)
-            y = tyi * ty + np.arange(ty)
-            x, y = x[x < nx], y[y < ny]
-            hit[zs:ze, y[0]:y[-1] + 1, x[0]:x[-1] + 1] += 1
-        assert (hit == 1).all()
-        # red at H position (lx, ly) reads U at (lx + 1 +- 1, ly + 1 +- 1)
-        lx, ly = np.meshgrid(np.arange(HX), np.arange(HY))
-        assert (lx + 2).max() <= UX - 1 and (ly + 2).max() <= UY - 1 and lx.min() >= 0
-        # black at tile position reads H at (lx + 1 +- 1, ly + 1 +- 1)
-        assert TX + 1 <= HX - 1 and ty + 1 <= HY - 1
+            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * GS_ZC
+            ze = min(zs + GS_ZC, nz)
+            x = x0 + np.arange(tx)
+            y = y0 + np.arange(ty)
+            X, Y = np.meshgrid(x, y, indexing="xy")
+            ok = (X < nx) & (Y < ny)
+            fx, fy = x0 - 2 + frame[:, 0], y0 - 2 + frame[:, 1]
+            fin = (fx >= 0) & (fy >= 0) & (fx < nx) & (fy < ny)
+            gh = fin & (((fx == 0) & ((fy >= y0) | (fy == 0)) & (fy < y0 + ty)) | ((fy == 0) & (fx >= x0) & (fx < x0 + tx)))
+            planes = list(range(zs, ze)) + ([0] if zs == 1 else [])
+            for q in planes:
+                np.add.at(hit, (q, Y[ok], X[ok]), 1)
+                np.add.at(hit, (q, fy[gh], fx[gh]), 1)
+        assert (hit == 1).all(), (nz, ny, nx, np.argwhere(hit != 1)[:5])
