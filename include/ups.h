@@ -50,6 +50,17 @@
  *   - Real arrays are C-contiguous [component][z][y][x] (x fastest), in the
  *     plan's precision (double for UPS_F64, float for UPS_F32), aligned to
  *     2 * sizeof(element) bytes.
+ *   - Observability.  Host calls that enqueue work open roctx ranges
+ *     (rocprofv3 --marker-trace): ups_plan_setup, ups_solve and
+ *     ups_solve_noalloc, with one range per pass inside ("ups:xfwd",
+ *     "ups:yfwd", "ups:zconv", "ups:yinv", "ups:xinv"), ups_batch_solve,
+ *     ups_mg_cycle and ups_autotune.  A range covers the host call that
+ *     enqueues the work; the kernels follow on the stream.  The environment
+ *     variable UPS_LOG_LEVEL (read once per process) sends lines "[ups] ..."
+ *     to stderr: 0 or unset, nothing; 1, every failing call with its status
+ *     and message; 2, also the decisions of plan, batch and cycle creation
+ *     and of the autotuner (kernels, schedule, buffer sizes); 3, also every
+ *     solve, batch launch and cycle.
  */
 #ifndef UPS_H
 #define UPS_H

@@ -30,8 +30,10 @@ OBJ = os.path.join(PKG, "_build")
 OBJ_SAN = os.path.join(OBJ, "san")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["passes_f32.hip", "passes_f32m.hip", "passes_f64.hip", "passes.cpp", "green.hip", "debug.hip",
-           "multigrid.hip", "capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp"]
-HOST_SOURCES = ["capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp"]
+           "multigrid.hip", "capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp", "trace.cpp"]
+HOST_SOURCES = ["capi.cpp", "batch.cpp", "autotune.cpp", "mg_capi.cpp", "trace.cpp"]
+# roctx ranges (trace.hpp); the library's run path already holds the ROCm lib directory
+LINK_LIBS = ["-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocprofiler-sdk-roctx"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -71,7 +73,7 @@ def _compile(src, verbose, objdir=OBJ, extra=()):
 
 def _link(objs, out, extra=(), verbose=False):
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + list(extra) + ["-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + list(extra) + ["-o", tmp] + objs + LINK_LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

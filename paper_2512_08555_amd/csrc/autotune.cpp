@@ -21,6 +21,7 @@
 #include "../../include/ups.h"
 #include "passes.hpp"
 #include "plan.hpp"
+#include "trace.hpp"
 
 using namespace ups;
 
@@ -143,6 +144,7 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
   const uintptr_t al = 2 * plan->g.elem - 1;
   if ((reinterpret_cast<uintptr_t>(f) | reinterpret_cast<uintptr_t>(u)) & al)
     return set_error(UPS_ERR_INVALID_ARG, "f and u are misaligned");
+  TraceRange range("ups_autotune");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const PlanGeom& g = plan->g;
   const int len[5] = {g.mx, g.my, g.mz, g.my, g.mx};
@@ -199,12 +201,15 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
       plan->var[k] = v;
       float ms = 0.f;
       err = time_solves(&ms);
+      logf(2, "autotune plan %p pass %d: %s %.4f ms per solve (current %s %.4f ms)", static_cast<void*>(plan), k,
+           v->name, double(ms), best->name, double(best_ms));
       if (err == hipSuccess && ms < 0.99f * best_ms) {
         best_ms = ms;
         best = v;
       }
     }
     plan->var[k] = best;
+    logf(2, "autotune plan %p pass %d: keeps %s", static_cast<void*>(plan), k, best->name);
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
     g_cache[tune_key(kKinds[k], g)] = best->name;
@@ -238,6 +243,8 @@ ups_status ups_autotune(ups_plan_t plan, const void* f, void* u, void* stream, d
     }
     plan->slab = best_slab;
     plan->use_side = best_side;
+    logf(2, "autotune plan %p: schedule slab %d, second stream %d (%.4f ms per solve)", static_cast<void*>(plan),
+         best_slab, int(best_side), double(best_ms));
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -26,6 +26,7 @@
 #include "green.hpp"
 #include "passes.hpp"
 #include "plan.hpp"
+#include "trace.hpp"
 
 using namespace ups;
 
@@ -207,6 +208,15 @@ ups_status ups_batch_create(const ups_problem* probs, int count, ups_batch_t* ou
   off = align_up(off + sizeof(void*) * 2 * count, 256);
   b->green_bytes = off;
   b->work_bytes = std::max(work_off, setup_max);
+  if (log_level() >= 2) {
+    logf(2, "batch %p: %d problems; grouped launches per pass %zu %zu %zu %zu %zu; G_hat buffer %zu B, work %zu B",
+         static_cast<void*>(b), count, b->launches[0].size(), b->launches[1].size(), b->launches[2].size(),
+         b->launches[3].size(), b->launches[4].size(), b->green_bytes, b->work_bytes);
+    for (int k = 0; k < 5; ++k)
+      for (const Launch& L : b->launches[k])
+        logf(2, "batch %p pass %d: %s, %zu problem(s), %u blocks, %.0f model bytes", static_cast<void*>(b), k,
+             L.var->name, L.probs.size(), L.nblocks, L.bytes);
+  }
   *out = b;
   set_error(UPS_OK, "");
   return UPS_OK;
@@ -331,6 +341,8 @@ ups_status ups_batch_solve(ups_batch_t b, const void* const* f, void* const* u, 
     ptrs.p[2 * i] = f[i];
     ptrs.p[2 * i + 1] = u[i];
   }
+  TraceRange range("ups_batch_solve");
+  logf(3, "batch solve %p: %d problems, stream %p", static_cast<void*>(b), n, stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void** io = reinterpret_cast<const void**>(static_cast<char*>(b->green) + b->off_io);
   hipLaunchKernelGGL(k_set_io, dim3((2 * n + 255) / 256), dim3(256), 0, st, ptrs, 2 * n, io);

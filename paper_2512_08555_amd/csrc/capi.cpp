@@ -16,6 +16,7 @@
 #include "green.hpp"
 #include "passes.hpp"
 #include "plan.hpp"
+#include "trace.hpp"
 
 using namespace ups;
 
@@ -29,6 +30,7 @@ ups_status fail(ups_status s, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+  if (s != UPS_OK) logf(1, "error %d: %s", int(s), buf);
   return s;
 }
 ups_status ok() {
@@ -376,7 +378,11 @@ hipError_t enqueue_colpass(const PlanGeom& g, const PassVariant* v, const PassAr
 
 ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], const PassArgs& a, int slab,
                          const void* f, void* u, void* work, hipStream_t st, const SideStream* side) {
-  var[0]->launch(a, f, work, st);
+  static const char* const kRange[5] = {"ups:xfwd", "ups:yfwd", "ups:zconv", "ups:yinv", "ups:xinv"};
+  {
+    TraceRange r(kRange[0]);
+    var[0]->launch(a, f, work, st);
+  }
   const int ns = slab_count(g, slab);
   if (side && side->s && ns > 1 && ns <= SideStream::kMaxSlabs) {
     // pipeline: the y passes on st, the z pass on the side stream, so that a
@@ -389,18 +395,27 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
       if (ee == hipSuccess) ee = r;
     };
     for (int s = 0; s < ns; ++s) b[s] = slab_args(g, a, slab, s, work, &ws[s]);
-    for (int s = 0; s < ns; ++s) {
-      chk(enqueue_colpass(g, var[1], b[s], ws[s], st));
-      chk(hipEventRecord(side->ev[2 * s], st));
-      chk(hipStreamWaitEvent(side->s, side->ev[2 * s], 0));
-      chk(enqueue_colpass(g, var[2], b[s], ws[s], side->s));
-      chk(hipEventRecord(side->ev[2 * s + 1], side->s));
+    {
+      TraceRange r("ups:yfwd+zconv (slab pipeline)");
+      for (int s = 0; s < ns; ++s) {
+        chk(enqueue_colpass(g, var[1], b[s], ws[s], st));
+        chk(hipEventRecord(side->ev[2 * s], st));
+        chk(hipStreamWaitEvent(side->s, side->ev[2 * s], 0));
+        chk(enqueue_colpass(g, var[2], b[s], ws[s], side->s));
+        chk(hipEventRecord(side->ev[2 * s + 1], side->s));
+      }
     }
-    for (int s = 0; s < ns; ++s) {
-      chk(hipStreamWaitEvent(st, side->ev[2 * s + 1], 0));
-      chk(enqueue_colpass(g, var[3], b[s], ws[s], st));
+    {
+      TraceRange r(kRange[3]);
+      for (int s = 0; s < ns; ++s) {
+        chk(hipStreamWaitEvent(st, side->ev[2 * s + 1], 0));
+        chk(enqueue_colpass(g, var[3], b[s], ws[s], st));
+      }
     }
-    var[4]->launch(a, work, u, st);
+    {
+      TraceRange r(kRange[4]);
+      var[4]->launch(a, work, u, st);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = ee;
     if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "solve enqueue failed: %s", hipGetErrorString(e));
@@ -425,14 +440,26 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
       // launches run beside the z pass (bound by arithmetic) rather than the
       // y pass (bound by memory); FP64 forks after the x pass
       const int late = g.f64 ? 0 : 1;
-      if (late) var[1]->launch(am, wm, wm, st);
+      if (late) {
+        TraceRange r(kRange[1]);
+        var[1]->launch(am, wm, wm, st);
+      }
       hipError_t ee = hipEventRecord(side->fork, st);
       if (ee == hipSuccess) ee = hipStreamWaitEvent(side->s, side->fork, 0);
-      for (int p = 0; p < 3 && ee == hipSuccess; ++p) nv[p]->launch(ar, wr, wr, side->s);
+      {
+        TraceRange r("ups:last columns (second stream)");
+        for (int p = 0; p < 3 && ee == hipSuccess; ++p) nv[p]->launch(ar, wr, wr, side->s);
+      }
       if (ee == hipSuccess) ee = hipEventRecord(side->join, side->s);
-      for (int p = 1 + late; p <= 3 && ee == hipSuccess; ++p) var[p]->launch(am, wm, wm, st);
+      for (int p = 1 + late; p <= 3 && ee == hipSuccess; ++p) {
+        TraceRange r(kRange[p]);
+        var[p]->launch(am, wm, wm, st);
+      }
       if (ee == hipSuccess) ee = hipStreamWaitEvent(st, side->join, 0);
-      if (ee == hipSuccess) var[4]->launch(a, work, u, st);
+      if (ee == hipSuccess) {
+        TraceRange r(kRange[4]);
+        var[4]->launch(a, work, u, st);
+      }
       hipError_t e = hipGetLastError();
       if (e == hipSuccess) e = ee;
       if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "solve enqueue failed: %s", hipGetErrorString(e));
@@ -443,9 +470,13 @@ ups_status enqueue_solve(const PlanGeom& g, const PassVariant* const var[5], con
   for (int s = 0; s < ns && e == hipSuccess; ++s) {
     void* ws = nullptr;
     const PassArgs b = slab_args(g, a, slab, s, work, &ws);
-    for (int p = 1; p <= 3 && e == hipSuccess; ++p) e = enqueue_colpass(g, var[p], b, ws, st, side);
+    for (int p = 1; p <= 3 && e == hipSuccess; ++p) {
+      TraceRange r(kRange[p]);
+      e = enqueue_colpass(g, var[p], b, ws, st, side);
+    }
   }
   if (e == hipSuccess) {
+    TraceRange r(kRange[4]);
     var[4]->launch(a, work, u, st);
     e = hipGetLastError();
   }
@@ -514,6 +545,12 @@ ups_status ups_plan_create(const ups_problem* prob, ups_plan_t* out) {
       return fail(UPS_ERR_UNSUPPORTED, "no kernel for pass %d at length %d", i, len[i]);
     }
   }
+  logf(2,
+       "plan %p: %d x %d x %d (x, y, z) %s, %d component(s), padded %d x %d x %d; kernels %s %s %s %s %s; "
+       "slab %d, second stream %d, Nyquist column packed %d, guards %d; G_hat buffer %zu B, work %zu B",
+       static_cast<void*>(p), g.nx, g.ny, g.nz, g.f64 ? "FP64" : "FP32", g.ncomp, g.mx, g.my, g.mz,
+       p->var[0]->name, p->var[1]->name, p->var[2]->name, p->var[3]->name, p->var[4]->name, p->slab,
+       int(p->use_side), int(g.nyq), int(guards), g.green_bytes, g.work_bytes);
   *out = p;
   return ok();
 }
@@ -539,6 +576,7 @@ ups_status ups_plan_setup(ups_plan_t plan, void* green, size_t green_bytes, void
   int dev = 0;
   ups_status s = check_device(&dev);
   if (s != UPS_OK) return s;
+  TraceRange range("ups_plan_setup");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* gb = static_cast<char*>(green);
   hipError_t e = build_twiddles(g.f64, g.mx, gb + g.off_twx, work, st);
@@ -648,6 +686,8 @@ static ups_status guarded_solve(ups_plan_t plan, const void* f, void* u, hipStre
 ups_status ups_solve(ups_plan_t plan, const void* f, void* u, void* stream) {
   ups_status s = check_io(plan, f, u);
   if (s != UPS_OK) return s;
+  TraceRange range("ups_solve");
+  logf(3, "solve plan %p f %p u %p stream %p", static_cast<void*>(plan), f, static_cast<void*>(u), stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   bool bad = false;
   if (plan->check_finite || plan->guards) {
@@ -715,6 +755,9 @@ ups_status ups_solve_noalloc(ups_plan_t plan, const void* f, void* u, void* stre
   void* W = nullptr;
   hipError_t e = scratch_address(cur, &W);
   if (e != hipSuccess) return fail(UPS_ERR_DEVICE, "hipGetSymbolAddress: %s", hipGetErrorString(e));
+  TraceRange range("ups_solve_noalloc");
+  logf(3, "solve (no allocation) plan %p f %p u %p stream %p", static_cast<void*>(plan), f, static_cast<void*>(u),
+       stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (plan->check_finite) {
     bool bad = false;

@@ -12,6 +12,7 @@
 #include "../../include/ups.h"
 #include "mg.hpp"
 #include "plan.hpp"
+#include "trace.hpp"
 
 using namespace ups;
 
@@ -116,6 +117,13 @@ ups_status ups_mg_create(ups_plan_t coarse, const ups_mg_hierarchy* hier, ups_mg
     off = align256(off + (size_t)(b.mx + 1) * (b.my + 1) * (b.mz + 1) * el);
   }
   mg->bytes = off;
+  if (log_level() >= 2) {
+    logf(2, "cycle %p: %d refined level(s) over plan %p, work %zu B", static_cast<void*>(mg), mg->levels,
+         static_cast<void*>(coarse), mg->bytes);
+    for (int k = 0; k <= mg->levels; ++k)
+      logf(2, "cycle %p level %d: %d x %d x %d nodes, h %.6g", static_cast<void*>(mg), k, mg->grid[k].nx,
+           mg->grid[k].ny, mg->grid[k].nz, mg->h[k]);
+  }
   *out = mg;
   return set_error(UPS_OK, "");
 }
@@ -150,6 +158,8 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   if (s != UPS_OK) return s;
   if (nu1 < 0 || nu1 > 64 || nu2 < 0 || nu2 > 64)
     return set_error(UPS_ERR_INVALID_ARG, "nu1 and nu2 must be 0 .. 64");
+  TraceRange range("ups_mg_cycle");
+  logf(3, "cycle %p: V(%d, %d), stream %p", static_cast<void*>(mg), nu1, nu2, stream);
   const bool f64 = mg->plan->g.f64;
   const size_t el = mg->plan->g.elem;
   const int L = mg->levels;
