@@ -308,6 +308,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=2, help="seed of the headline source (blobs plus noise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -327,7 +328,7 @@ def main():
 
     n = args.n
     h = 1.0 / n
-    f64 = workloads.config_blobs_noise(n, 2)
+    f64 = workloads.config_blobs_noise(n, args.seed)
     f32_host = f64.astype(np.float32)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
