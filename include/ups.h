@@ -256,9 +256,17 @@ const char* ups_plan_kernel(ups_plan_t plan, int pass);
  * is 0) and returns how many exist (0 for bad arguments).  The first one is
  * the default a new plan uses when no tuning result is cached.  Listed are
  * the variants for unbounded and periodic directions; a forward pass along
- * an even or odd direction runs the mirrored-fill variant of its length
- * (names ending in "_e"), the only choice ups_plan_set_kernel accepts there. */
+ * an even or odd direction runs a mirrored-fill variant of its length
+ * (names ending in "_e", listed by ups_kernel_fill_variants), the only
+ * choices ups_plan_set_kernel accepts there. */
 int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap);
+
+/* The mirrored-fill variants of forward pass 0..2 (x, y, z) for an even or
+ * odd direction of padded length `len` (Sec. 2.2: the second half of each
+ * line is the mirror image of the first, with the sign of the symmetry,
+ * instead of the zero padding), as ups_kernel_variants lists the others;
+ * the first one is the default.  0 for the inverse passes. */
+int ups_kernel_fill_variants(int pass, int prec, int len, const char** names, int cap);
 
 /* Select the compiled variant `name` for pass 0..4 (names as returned by
  * ups_plan_kernel; used by tuning).  INVALID_ARG if no such variant exists

@@ -68,6 +68,7 @@ SIGNATURES = {
     "ups_plan_kernel": (C.c_char_p, [C.c_void_p, C.c_int]),
     "ups_plan_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
     "ups_kernel_variants": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_char_p), C.c_int]),
+    "ups_kernel_fill_variants": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_char_p), C.c_int]),
     "ups_run_pass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ups_plan_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_longlong), C.POINTER(C.c_size_t), C.POINTER(C.c_longlong)]),

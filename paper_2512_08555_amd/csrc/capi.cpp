@@ -830,16 +830,24 @@ ups_status ups_plan_set_kernel(ups_plan_t plan, int pass, const char* name) {
   return ok();
 }
 
-int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap) {
+static int list_variants(int pass, int prec, int len, int fill, const char** names, int cap) {
   if (pass < 0 || pass > 4 || (prec != UPS_F64 && prec != UPS_F32) || cap < 0 || (cap > 0 && !names)) return 0;
   const PassKind kinds[5] = {PASS_XFWD, PASS_YFWD, PASS_ZCONV, PASS_YINV, PASS_XINV};
   int n = 0;
   for (const PassVariant& v : pass_variants()) {
-    if (v.kind != kinds[pass] || v.is_f64 != (prec == UPS_F64 ? 1 : 0) || v.length != len || v.fill) continue;
+    if (v.kind != kinds[pass] || v.is_f64 != (prec == UPS_F64 ? 1 : 0) || v.length != len || v.fill != fill) continue;
     if (n < cap) names[n] = v.name;
     ++n;
   }
   return n;
+}
+
+int ups_kernel_variants(int pass, int prec, int len, const char** names, int cap) {
+  return list_variants(pass, prec, len, 0, names, cap);
+}
+
+int ups_kernel_fill_variants(int pass, int prec, int len, const char** names, int cap) {
+  return list_variants(pass, prec, len, 1, names, cap);
 }
 
 ups_status ups_plan_set_slab(ups_plan_t plan, int columns) {

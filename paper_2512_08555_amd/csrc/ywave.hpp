@@ -19,7 +19,10 @@
 
 namespace ups {
 
-template <typename T, int E, int CW>
+// FILL: the y direction is even or odd (a.fill_y = +1 or -1, ny = M/2):
+// rows n >= M/2 are a.fill_y times row M - 1 - n, read from the column's LDS
+// slot, and the first stage is full.
+template <typename T, int E, int CW, bool FILL = false>
 __device__ __forceinline__ void ywfwd_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
@@ -80,7 +83,15 @@ __device__ __forceinline__ void ywfwd_body(cx<T>* __restrict__ W, const PassArgs
     constexpr int j = decltype(jj)::value;
     v[j] = slot[lane + 64 * j];
   });
-  zw_forward<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+  if constexpr (FILL) {
+    // row lane + 64 j, j >= E/2, mirrors row (63 - lane) + 64 (E - 1 - j)
+    const T fs = T(a.fill_y);
+    static_for<E / 2, E>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      v[j] = scale(slot[(63 - lane) + 64 * (E - 1 - j)], fs);
+    });
+  }
+  zw_forward<T, E, false, FILL>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
   // output rows k = lane + base(i) (base a multiple of 64: a wave's rows lie
   // in one half), half h through the slots
   static_for<0, 2>([&](auto hh) {
@@ -101,30 +112,35 @@ __device__ __forceinline__ void ywfwd_body(cx<T>* __restrict__ W, const PassArgs
   });
 }
 
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool FILL = false>
 __global__ void __launch_bounds__(64 * CW) k_ywfwd(cx<T>* __restrict__ W, PassArgs a) {
-  ywfwd_body<T, E, CW>(W, a, blockIdx.x);
+  ywfwd_body<T, E, CW, FILL>(W, a, blockIdx.x);
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool FILL = false>
 __global__ void __launch_bounds__(64 * CW) k_ywfwd_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  ywfwd_body<T, E, CW>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  ywfwd_body<T, E, CW, FILL>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool FILL = false>
 void launch_ywfwd(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_ywfwd<T, E, CW>), dim3(ypass_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_ywfwd<T, E, CW, FILL>), dim3(ypass_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int CW>
+template <typename T, int E, int CW, bool FILL = false>
 void launchg_ywfwd(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_ywfwd_g<T, E, CW>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+  hipLaunchKernelGGL((k_ywfwd_g<T, E, CW, FILL>), dim3(nblocks), dim3(64 * CW), 0, s, g);
 }
 #define YFW(T, E, CW)                                                                             \
   PassVariant{PASS_YFWD, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW, zwave_lds_bytes<T, E, CW>(),   \
               "yfwd_" #T "_w" #E "_c" #CW, &launch_ywfwd<T, E, CW>, &launchg_ywfwd<T, E, CW>}
+// the y forward pass along an even or odd direction (mirrored fill, suffix "_e")
+#define YFWE(T, E, CW)                                                                            \
+  PassVariant{PASS_YFWD, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW, zwave_lds_bytes<T, E, CW>(),   \
+              "yfwd_" #T "_w" #E "_c" #CW "_e", &launch_ywfwd<T, E, CW, true>,                    \
+              &launchg_ywfwd<T, E, CW, true>, 1}
 
 // PRE: issue the loads of both halves at the start (the second half waits
 // in registers while the first is read out of LDS).  TB: twiddles of the

@@ -121,17 +121,19 @@ __device__ __forceinline__ void zw_fill_tables(cx<T>* tab, const cx<T>* tw, int 
 }
 
 // Forward transform of one line held by a wave: on entry v[j] (j < E/2)
-// holds row lane + 64 j (rows M/2 .. M-1 are the zero padding); on exit
-// register r A + m2 holds X[lane + 64 r + E^2 m2].  xf: the wave's LDS
-// exchange area; trow(j, x) = w_M^(2^j x).
+// holds row lane + 64 j (rows M/2 .. M-1 are the zero padding; FULL: every
+// v[j] holds its row, the first stage is a full DFT_E); on exit register
+// r A + m2 holds X[lane + 64 r + E^2 m2].  xf: the wave's LDS exchange area;
+// trow(j, x) = w_M^(2^j x).
 // TB: stage-2 twiddles from the ZTab tables at tab (LDS), else by products
 // of table rows.
-template <typename T, int E, bool TB, typename TR>
+template <typename T, int E, bool TB, bool FULL = false, typename TR>
 __device__ __forceinline__ void zw_forward(cx<T> (&v)[E], T* xf, int lane, TR trow, const cx<T>* tab) {
   using Z = ZWave<E>;
   constexpr int A = Z::A, R3 = Z::R3, S1 = Z::S1, P2 = Z::P2;
   // stage 1: DFT_E over j, times w_M^(l k1) = T[k1][l]
-  dft_half_in<E, -1>(v);
+  if constexpr (FULL) dft<E, -1>(v);
+  else dft_half_in<E, -1>(v);
   twiddle_run<E, false>(v, [&](int j) { return trow(j, lane); });
   // exchange 1: (l, k1) at k1 S1 + l; lane (k1, l1) reads l2 at k1 S1 + l1 + A l2
   {
@@ -246,7 +248,10 @@ __device__ __forceinline__ void zw_inverse(cx<T> (&v)[E], T* xf, int lane, TR tr
 // GP: load this lane's G_hat values at the start (they then share the
 // latency of the tile loads) instead of after the forward transform.
 // TB: twiddles of stage 2 and of the inverse stages A and B from LDS tables.
-template <typename T, int E, int CW, bool GP, bool TB>
+// FILL: the z direction is even or odd (a.fill_z = +1 or -1, nz = M/2):
+// rows n >= M/2 of the line are a.fill_z times row M - 1 - n instead of the
+// zero padding, read from the column's LDS slot, and the first stage is full.
+template <typename T, int E, int CW, bool GP, bool TB, bool FILL = false>
 __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs& a, unsigned bx) {
   using Z = ZWave<E>;
   constexpr int M = Z::M, A = Z::A, E2 = Z::E2;
@@ -342,7 +347,15 @@ __device__ __forceinline__ void zwave_body(cx<T>* __restrict__ W, const PassArgs
     constexpr int j = decltype(jj)::value;
     v[j] = slot[lane + 64 * j];
   });
-  zw_forward<T, E, TB>(v, xf, lane, trow, ztab);
+  if constexpr (FILL) {
+    // row lane + 64 j, j >= E/2, mirrors row (63 - lane) + 64 (E - 1 - j)
+    const T fs = T(a.fill_z);
+    static_for<E / 2, E>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      v[j] = scale(slot[(63 - lane) + 64 * (E - 1 - j)], fs);
+    });
+  }
+  zw_forward<T, E, TB, FILL>(v, xf, lane, trow, ztab);
   // G_hat: lane L, register r A + m2 holds kz = L + 64 r + E^2 m2
   static_for<0, E>([&](auto ii) {
     constexpr int i = decltype(ii)::value;
@@ -443,32 +456,32 @@ void launch_zpair_t(const PassArgs& a, void* W, hipStream_t s) {
 
 // OCC: minimum waves per SIMD asked of the register allocator (1: no
 // constraint; 8 caps registers at 64, spilling a few values to scratch).
-template <typename T, int E, int CW, bool GP, int OCC, bool TB>
+template <typename T, int E, int CW, bool GP, int OCC, bool TB, bool FILL = false>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_zwave(cx<T>* __restrict__ W, PassArgs a) {
-  zwave_body<T, E, CW, GP, TB>(W, a, blockIdx.x);
+  zwave_body<T, E, CW, GP, TB, FILL>(W, a, blockIdx.x);
 }
-template <typename T, int E, int CW, bool GP, bool TB>
+template <typename T, int E, int CW, bool GP, bool TB, bool FILL = false>
 __global__ void __launch_bounds__(64 * CW) k_zwave_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
-  zwave_body<T, E, CW, GP, TB>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
+  zwave_body<T, E, CW, GP, TB, FILL>(static_cast<cx<T>*>(group_out(g, e)), e.a, lin);
 }
 
 template <typename T, int CW>
 inline unsigned zwave_blocks(const PassArgs& a) {
   return zmap_blocks(cdiv(a.kx, CW), a.my, a.ncomp, col_slots<T, CW>(cdiv(a.kx, CW)));
 }
-template <typename T, int E, int CW, bool GP, int OCC, bool TB>
+template <typename T, int E, int CW, bool GP, int OCC, bool TB, bool FILL = false>
 void launch_zwave(const PassArgs& a, const void*, void* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave<T, E, CW, GP, OCC, TB>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
+  hipLaunchKernelGGL((k_zwave<T, E, CW, GP, OCC, TB, FILL>), dim3(zwave_blocks<T, CW>(a)), dim3(64 * CW), 0, s,
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int CW, bool GP, bool TB>
+template <typename T, int E, int CW, bool GP, bool TB, bool FILL = false>
 void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_zwave_g<T, E, CW, GP, TB>), dim3(nblocks), dim3(64 * CW), 0, s, g);
+  hipLaunchKernelGGL((k_zwave_g<T, E, CW, GP, TB, FILL>), dim3(nblocks), dim3(64 * CW), 0, s, g);
 }
 
 // P = E, Q = 64 (line length 64 E), tile = CW columns, nch = 0 marks the
@@ -482,5 +495,10 @@ void launchg_zwave(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
 #define ZWO(T, E, CW) ZWV(T, E, CW, "_o8", false, 8, false)
 #define ZWG(T, E, CW) ZWV(T, E, CW, "_g", true, 1, false)
 #define ZWT(T, E, CW) ZWV(T, E, CW, "_t", false, 1, true)
+// the z pass along an even or odd direction (mirrored fill, suffix "_e")
+#define ZWE(T, E, CW, TB)                                                                         \
+  PassVariant{PASS_ZCONV, is64<T>(), 64 * E, E, 64, CW, 0, 64 * CW,                               \
+              zwave_lds_bytes<T, E, CW, TB>(), "zconv_" #T "_w" #E "_c" #CW "_e",                 \
+              &launch_zwave<T, E, CW, false, 1, TB, true>, &launchg_zwave<T, E, CW, false, TB, true>, 1}
 
 }  // namespace ups

@@ -237,13 +237,15 @@ class Plan:
         return w.view(self.ncomp, nz, my, lay["pitch"])
 
 
-def kernel_variants(k, prec, length):
-    """Names of the compiled kernel variants of pass k for a padded length."""
+def kernel_variants(k, prec, length, fill=False):
+    """Names of the compiled kernel variants of pass k for a padded length
+    (fill: the mirrored-fill forward variants of an even or odd direction)."""
     L = capi.lib()
     p = capi.UPS_F64 if prec == "f64" else capi.UPS_F32
-    n = L.ups_kernel_variants(int(k), p, int(length), None, 0)
+    fn = L.ups_kernel_fill_variants if fill else L.ups_kernel_variants
+    n = fn(int(k), p, int(length), None, 0)
     arr = (C.c_char_p * max(n, 1))()
-    L.ups_kernel_variants(int(k), p, int(length), arr, n)
+    fn(int(k), p, int(length), arr, n)
     return [arr[i].decode() for i in range(n)]
 
 

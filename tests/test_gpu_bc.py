@@ -142,7 +142,8 @@ def test_even_odd_mixes_match_oracle(bc, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_even_odd_at_long_lines(prec):
-    # mirrored fill at the lengths 512 and 1024 (the four-step kernels)
+    # mirrored fill at the lengths 512 and 1024 (wave-per-line y and z
+    # kernels, the four-step x kernel)
     shape, bc = (64, 16, 512), ("even", "odd", "even")
     h = 1.0 / 512
     pad = _pads(shape, bc, prec)
