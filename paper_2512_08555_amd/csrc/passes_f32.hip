@@ -39,10 +39,11 @@ std::vector<PassVariant> variants_f32_pow2() {
       YI(float, 32, 32, 8, 1), YI(float, 32, 32, 8, 2), YI(float, 32, 32, 16, 2),
       YI(float, 32, 32, 16, 4), YI(float, 32, 32, 4, 1), YI(float, 32, 32, 4, 2),
       YF(float, 32, 32, 2, 1), YI(float, 32, 32, 2, 1),
-      // even and odd directions: the wave-per-line y and z forward passes at
-      // 512 and 1024 (ahead of the four-step ones below, so the defaults)
+      // even and odd directions: the wave-per-line forward passes (y and z at
+      // 512 and 1024, x at 1024), ahead of the four-step ones below, so the defaults
       ZWE(float, 8, 16, true), ZWE(float, 8, 1, false), YFWE(float, 8, 16), YFWE(float, 8, 1),
       ZWE(float, 16, 16, true), ZWE(float, 16, 1, false), YFWE(float, 16, 16), YFWE(float, 16, 1),
+      XFWE(float, 8, 4),   // mx = 1024
       // even and odd directions, mx/my/mz = 32 .. 1024
       FILL_VARIANTS(float, 4, 4, 16, 1, 4, 8, 16, 1, 4, 8, 16, 1),
       FILL_VARIANTS(float, 4, 8, 16, 1, 8, 8, 16, 1, 8, 8, 16, 1),

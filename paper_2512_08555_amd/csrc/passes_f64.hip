@@ -35,10 +35,11 @@ std::vector<PassVariant> variants_f64() {
       YFW(double, 16, 4), YFW(double, 16, 1),
       YI(double, 32, 32, 8, 2), YI(double, 32, 32, 8, 4),
       YF(double, 32, 32, 2, 1), YI(double, 32, 32, 2, 1),
-      // even and odd directions: the wave-per-line y and z forward passes at
-      // 512 and 1024 (ahead of the four-step ones below, so the defaults)
+      // even and odd directions: the wave-per-line forward passes (y and z at
+      // 512 and 1024, x at 1024), ahead of the four-step ones below, so the defaults
       ZWE(double, 8, 4, false), ZWE(double, 8, 1, false), YFWE(double, 8, 8), YFWE(double, 8, 1),
       ZWE(double, 16, 8, false), ZWE(double, 16, 1, false), YFWE(double, 16, 8), YFWE(double, 16, 1),
+      XFWE(double, 8, 8),   // mx = 1024
       // even and odd directions, mx/my/mz = 32 .. 1024
       FILL_VARIANTS(double, 4, 4, 8, 1, 4, 8, 8, 1, 4, 8, 8, 1),
       FILL_VARIANTS(double, 4, 8, 8, 1, 8, 8, 8, 1, 8, 8, 8, 1),

@@ -136,7 +136,11 @@ constexpr int xwfwd_slot() {
   return a > b ? a : b;
 }
 
-template <typename T, int E, int RW>
+// FILL: the x direction is even or odd (a.fill_x = +1 or -1, nx = L): the
+// packed line's second half holds the mirror image, Z[m] = fill_x times the
+// swapped pair of Z[L - 1 - m] (x[2 L - 1 - 2 m] + i x[2 L - 2 - 2 m]), loaded
+// from the row again in reversed order, and the first stage is full.
+template <typename T, int E, int RW, bool FILL = false>
 __device__ __forceinline__ void xwfwd_body(const T* __restrict__ f, cx<T>* __restrict__ W, const PassArgs& a,
                                            unsigned bx, unsigned by) {
   using Z = ZWave<E>;
@@ -186,7 +190,17 @@ __device__ __forceinline__ void xwfwd_body(const T* __restrict__ f, cx<T>* __res
       v[j] = val;
     });
   }
-  zw_forward<T, E, 0>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
+  if constexpr (FILL) {
+    // m = lane + 64 j (j >= E/2) mirrors m' = L - 1 - m = (63 - lane) + 64 (E - 1 - j)
+    const T fs = T(a.fill_x);
+    static_for<E / 2, E>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int mr = (63 - lane) + 64 * (E - 1 - j);
+      const cx<T> p = ld_cx<nt_load<0>()>(reinterpret_cast<const cx<T>*>(src + 2 * mr));
+      v[j] = cx<T>{fs * p.im, fs * p.re};
+    });
+  }
+  zw_forward<T, E, 0, FILL>(v, xf, lane, trow, static_cast<const cx<T>*>(nullptr));
   // register i holds Z[k], k = lane + base(i); the whole Z into LDS at k
   wave_fence();
   static_for<0, E>([&](auto ii) {
@@ -215,29 +229,29 @@ __device__ __forceinline__ void xwfwd_body(const T* __restrict__ f, cx<T>* __res
   }
 }
 
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool FILL = false>
 __global__ void __launch_bounds__(64 * RW) k_xwfwd(const T* __restrict__ f, cx<T>* __restrict__ W, PassArgs a) {
-  xwfwd_body<T, E, RW>(f, W, a, blockIdx.x, blockIdx.y);
+  xwfwd_body<T, E, RW, FILL>(f, W, a, blockIdx.x, blockIdx.y);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool FILL = false>
 __global__ void __launch_bounds__(64 * RW) k_xwfwd_g(GroupArgs g) {
   unsigned lin;
   bool live;
   const GroupEntry& e = group_entry(g, &lin, &live);
   if (!live) return;  // uniform over the workgroup, before any barrier
   const unsigned gx = unsigned(cdiv((long long)e.a.ny * e.a.nz, RW));
-  xwfwd_body<T, E, RW>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)), e.a,
-                       lin % gx, lin / gx);
+  xwfwd_body<T, E, RW, FILL>(static_cast<const T*>(group_in(g, e)), static_cast<cx<T>*>(group_out(g, e)), e.a,
+                             lin % gx, lin / gx);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool FILL = false>
 void launch_xwfwd(const PassArgs& a, const void* in, void* out, hipStream_t s) {
   dim3 grid(cdiv((long long)a.ny * a.nz, RW), a.ncomp);
-  hipLaunchKernelGGL((k_xwfwd<T, E, RW>), grid, dim3(64 * RW), 0, s, static_cast<const T*>(in),
+  hipLaunchKernelGGL((k_xwfwd<T, E, RW, FILL>), grid, dim3(64 * RW), 0, s, static_cast<const T*>(in),
                      static_cast<cx<T>*>(out), a);
 }
-template <typename T, int E, int RW>
+template <typename T, int E, int RW, bool FILL = false>
 void launchg_xwfwd(const GroupArgs& g, unsigned nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_xwfwd_g<T, E, RW>), dim3(nblocks), dim3(64 * RW), 0, s, g);
+  hipLaunchKernelGGL((k_xwfwd_g<T, E, RW, FILL>), dim3(nblocks), dim3(64 * RW), 0, s, g);
 }
 
 template <typename T, int E, int RW, bool ML>
@@ -283,6 +297,11 @@ constexpr int xwave_lds_bytes() {
   PassVariant{PASS_XFWD, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW,                               \
               xwfwd_lds_bytes<T, E, RW>(),                                                        \
               "xfwd_" #T "_w" #E "_r" #RW, &launch_xwfwd<T, E, RW>, &launchg_xwfwd<T, E, RW>}
+// the x forward pass along an even or odd direction (mirrored fill, suffix "_e")
+#define XFWE(T, E, RW)                                                                            \
+  PassVariant{PASS_XFWD, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW,                               \
+              xwfwd_lds_bytes<T, E, RW>(), "xfwd_" #T "_w" #E "_r" #RW "_e",                      \
+              &launch_xwfwd<T, E, RW, true>, &launchg_xwfwd<T, E, RW, true>, 1}
 #define XIWV(T, E, RW, SUF, ML)                                                                   \
   PassVariant{PASS_XINV, is64<T>(), 128 * E, E, 64, RW, 0, 64 * RW, xwave_lds_bytes<T, E, RW, ML>(), \
               "xinv_" #T "_w" #E "_r" #RW SUF, &launch_xwinv<T, E, RW, ML>, &launchg_xwinv<T, E, RW, ML>}
