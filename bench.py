@@ -209,6 +209,37 @@ def c2_leg(n=256, reps=10):
             "hbm_gbs_model": plan.model_bytes(-1) / (ms * 1e-3) / 1e9}
 
 
+def variants_leg(n=512, reps=10):
+    """The NEXT-row problem classes at the headline size (512^3 FP32, the
+    headline source): the sixth-order Mehrstellen kernel (all unbounded),
+    periodic z with unbounded x and y (the vortex-tube configuration), and
+    an even z direction.  Setup (G_hat build) and whole-solve times beside
+    the plain 7-point unbounded solve."""
+    import torch
+    from paper_2512_08555_amd import workloads
+    from paper_2512_08555_amd.solver import Plan
+    h = 1.0 / n
+    f = torch.from_numpy(workloads.config_blobs_noise(n, 2).astype(np.float32)).cuda()
+    u = torch.empty_like(f)
+    out = {}
+    cases = (("lgf2_unbounded", dict()),
+             ("mehr6_unbounded", dict(green="mehr6")),
+             ("per_z_unb_xy", dict(bc=("per", "unb", "unb"), pad=(2 * n, 2 * n, 2 * n))),
+             ("even_z_unb_xy", dict(bc=("even", "unb", "unb"), pad=(2 * n, 2 * n, 2 * n))))
+    for name, kw in cases:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan((n, n, n), h, "f32", **kw)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        ms = time_solve(plan, f, u, reps, 3)
+        out[name] = {"setup_ms": setup_ms, "ms_per_solve": ms, "pts_per_s": n ** 3 / (ms * 1e-3),
+                     "kernels": [plan.kernel(k) for k in range(5)]}
+        del plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def grad_leg(n=256, reps=5):
     """Differentiable workload: 256^3 FP32 forward solve + loss + backward
     through the hand-written adjoint (torch.autograd)."""
@@ -314,6 +345,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-mg", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Mehrstellen / periodic / even leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB copy kernel (for counter calibration runs)")
     args = ap.parse_args()
@@ -413,6 +445,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_mg:
         extra["multigrid"] = mg_leg(n)
+        torch.cuda.empty_cache()
+    if not args.no_variants:
+        extra["problem_classes"] = variants_leg(n)
         torch.cuda.empty_cache()
     if args.calibrate_copy:
         extra["copy_calibration"] = calibrate_copy()
