@@ -187,3 +187,21 @@ def test_cycle_with_a_periodic_coarse_plan():
     err = _compare(ud, us)
     print("  rel err %.2e" % err, flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_wide_level_matches_the_oracle(prec):
+    # a refined level 257 nodes wide along x: the fused smoother's widest
+    # tiles (256 x 8 in FP32, 128 x 16 in FP64) and a 33 x 41 ragged y-z section
+    n0 = (30, 24, 140)
+    patches = [((4, 4, 5), (20, 16, 128))]
+    print("[case] multigrid wide level %s %s %s" % (prec, n0, patches), flush=True)
+    mg, fs, u0, fd, ud = _setup(n0, patches, prec, 60)
+    assert mg.shapes[1] == (41, 33, 257)
+    us = [u.copy() for u in u0]
+    for nu in [(2, 2), (1, 1)]:
+        mg.cycle(fd, ud, *nu)
+        omg.vcycle(us, fs, patches, H0, *nu)
+    err = _compare(ud, us)
+    print("  rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]

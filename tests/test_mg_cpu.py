@@ -293,7 +293,8 @@ def test_fused_smoothing_frame_and_lds(shape):
         assert len({k, (k + 1) % 4, (k + 3) % 4, (k + 2) % 4}) == 4
 
 
-@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), []), ((33, 65, 513), [])])
+@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), []), ((33, 65, 513), []),
+                                                        ((30, 24, 140), [((4, 4, 5), (20, 16, 128))])])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_smoothing_writes_every_node_once(n0, patches, prec):
     # tiles from node 1 by chunks of 32 planes from plane 1 (the XCD-aware
