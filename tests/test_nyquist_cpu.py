@@ -53,3 +53,39 @@ def test_packed_plans_refuse_four_step_x_and_z_kernels_and_slabs():
     st = capi.lib().ups_plan_set_slab(p._h, 128)
     assert st == capi.UPS_ERR_UNSUPPORTED
     assert capi.lib().ups_plan_set_slab(p._h, 0) == capi.UPS_OK
+
+
+def test_nyquist_pair_identity():
+    # The identity the column-0 pair launch evaluates: for a real source the
+    # x-frequencies 0 and mx/2 of its spectrum are real along x, so after the
+    # y and z transforms F_0 and F_N are Hermitian in (ky, kz); with
+    # F_C = F_0 + i F_N and real G_hat lines G0, GN,
+    #   R(ky, kz) = F_C(ky, kz) (G0 + GN) / 2 + conj F_C(-ky, -kz) (G0 - GN) / 2
+    # equals G0 F_0 + i GN F_N, and the inverse of R is the solve's kx = 0
+    # part plus i times its kx = mx/2 part.  Checked with numpy FFTs on a
+    # random real field, independently of the kernels.
+    import numpy as np
+    rng = np.random.default_rng(7)
+    mz, my, mx = 12, 10, 16
+    f = rng.standard_normal((mz, my, mx))
+    X = np.fft.rfft(f, axis=2)                  # [z, y, kx], kx = 0 .. mx/2
+    F = np.fft.fft(np.fft.fft(X, axis=1), axis=0)
+    F0, FN = F[:, :, 0], F[:, :, mx // 2]
+    G0 = rng.standard_normal((mz, my))
+    GN = rng.standard_normal((mz, my))
+    # G_hat is even: G(-ky, -kz) = G(ky, kz)
+    rev = lambda a: np.roll(a[::-1, ::-1], 1, axis=(0, 1))
+    G0 = (G0 + rev(G0)) / 2
+    GN = (GN + rev(GN)) / 2
+    FC = F0 + 1j * FN
+    R = FC * (G0 + GN) / 2 + np.conj(rev(FC)) * (G0 - GN) / 2
+    assert np.allclose(R, G0 * F0 + 1j * GN * FN, rtol=0, atol=1e-12 * np.abs(F).max())
+    # the inverse: kx = 0 part plus i times the kx = mx/2 part, both real
+    r = np.fft.ifft(np.fft.ifft(R, axis=0), axis=1)
+    p0 = np.fft.ifft(np.fft.ifft(G0 * F0, axis=0), axis=1)
+    pN = np.fft.ifft(np.fft.ifft(GN * FN, axis=0), axis=1)
+    assert np.abs(p0.imag).max() < 1e-12 and np.abs(pN.imag).max() < 1e-12
+    assert np.allclose(r, p0.real + 1j * pN.real, rtol=0, atol=1e-12)
+    # a planted mistake (the conjugate of the unmirrored line) breaks it
+    Rbad = FC * (G0 + GN) / 2 + np.conj(FC) * (G0 - GN) / 2
+    assert not np.allclose(Rbad, G0 * F0 + 1j * GN * FN, rtol=0, atol=1e-6 * np.abs(F).max())
