@@ -115,3 +115,37 @@ def test_slot_holds_tile_and_exchange(E, CW):
     assert s >= 32 * E                          # the M/2 rows of the column
     assert 2 * s >= consts(E)[5]                # one exchange (floats)
     assert s % 16 == (16 // CW) % 16            # slot stride modulo 16 complex words
+
+
+@pytest.mark.parametrize("E", [8, 16])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_mirrored_fill_maps(E, sign):
+    # The wave-per-line forward kernels along an even or odd direction:
+    # lane l, register j >= E/2 holds row n = l + 64 j of the line of
+    # M = 64 E points, which is sign times row M - 1 - n, read from lane
+    # 63 - l, register E - 1 - j (a register below E/2, loaded as usual).
+    import numpy as np
+    M = 64 * E
+    lanes = np.arange(64)
+    for j in range(E // 2, E):
+        n = lanes + 64 * j
+        src = (63 - lanes) + 64 * (E - 1 - j)
+        assert np.array_equal(src, M - 1 - n) and src.max() < M // 2 and src.min() >= 0
+    # x: the packed complex line Z[m] = x[2m] + i x[2m+1] (L = M/2 = 32 E
+    # complex points, nx = L reals mirrored to 2 L) has
+    # Z[m] = sign * (Im Z[L-1-m] + i Re Z[L-1-m]) for m >= L/2
+    rng = np.random.default_rng(E)
+    L = 32 * E
+    x = rng.standard_normal(L)
+    ext = np.concatenate([x, sign * x[::-1]])
+    Z = ext[0::2] + 1j * ext[1::2]
+    m = np.arange(L // 2, L)
+    Zr = Z[L - 1 - m]
+    assert np.allclose(Z[m], sign * (Zr.imag + 1j * Zr.real), rtol=0, atol=0)
+    # the x kernel holds the packed line of Lx = 64 E complex points (2 Lx
+    # reals: E = 8 for 1024-point lines) as m = lane + 64 j; register
+    # j >= E/2 reads m' = Lx - 1 - m = (63 - lane) + 64 (E - 1 - j)
+    Lx = 64 * E
+    for j in range(E // 2, E):
+        mm = lanes + 64 * j
+        assert np.array_equal((63 - lanes) + 64 * (E - 1 - j), Lx - 1 - mm)
