@@ -30,6 +30,12 @@ hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
                                 hipStream_t st);
 
+// nu red-black iterations on u as mg_smooth_iterations, then r = f - Lap u
+// on the unknowns, the last iteration and the residual in one kernel (s: a
+// scratch array of the level's size, different from r)
+hipError_t mg_smooth_residual(bool f64, void* u, void* s, const void* f, void* r, MgGrid g, double h, int nu,
+                              hipStream_t st);
+
 // r = f - Lap u on the unknowns (the ghost layer of r is not written)
 hipError_t mg_residual(bool f64, const void* u, const void* f, void* r, MgGrid g, double h, hipStream_t st);
 

@@ -24,7 +24,7 @@ struct ups_mg_s {
   std::vector<double> h;          // spacing of each level
   std::vector<size_t> off_F;      // modified sources of levels 0 .. l-1
   std::vector<size_t> off_uhat;   // stored footprint of box k+1 at index k
-  size_t off_norm = 0, off_r = 0, bytes = 0;
+  size_t off_norm = 0, off_r = 0, off_s = 0, bytes = 0;
   void* work = nullptr;
 };
 
@@ -111,6 +111,8 @@ ups_status ups_mg_create(ups_plan_t coarse, const ups_mg_hierarchy* hier, ups_mg
   for (int k = 1; k <= mg->levels; ++k) rmax = std::max(rmax, nodes(mg->grid[k]) * el);
   mg->off_r = off;
   off = align256(off + rmax);
+  mg->off_s = off;
+  off = align256(off + rmax);
   for (int k = 0; k < mg->levels; ++k) {
     const MgBox& b = mg->box[k];
     mg->off_uhat.push_back(off);
@@ -171,6 +173,7 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   for (int k = 0; k < L; ++k) F[k] = wb + mg->off_F[k];
   F[L] = const_cast<void*>(f[L]);
   void* r = wb + mg->off_r;
+  void* sm = wb + mg->off_s;
   hipError_t e = hipSuccess;
   for (int k = 0; k < L && e == hipSuccess; ++k)
     e = hipMemcpyAsync(F[k], f[k], nodes(mg->grid[k]) * el, hipMemcpyDeviceToDevice, st);
@@ -179,9 +182,7 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
     const MgGrid& gp = mg->grid[k - 1];
     const MgBox& b = mg->box[k - 1];
     e = mg_fill_ghosts(f64, u[k], g, u[k - 1], gp, b, st);
-    // the residual buffer is the smoother's scratch until the residual
-    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], r, F[k], g, mg->h[k], nu1, st);
-    if (e == hipSuccess) e = mg_residual(f64, u[k], F[k], r, g, mg->h[k], st);
+    if (e == hipSuccess) e = mg_smooth_residual(f64, u[k], sm, F[k], r, g, mg->h[k], nu1, st);
     if (e == hipSuccess)
       e = mg_restrict(f64, u[k], r, g, u[k - 1], F[k - 1], wb + mg->off_uhat[k - 1], gp, b, mg->h[k - 1], st);
   }
@@ -192,7 +193,7 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   for (int k = 1; k <= L && e == hipSuccess; ++k) {
     const MgGrid& g = mg->grid[k];
     e = mg_prolong(f64, u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1], mg->box[k - 1], st);
-    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], r, F[k], g, mg->h[k], nu2, st);
+    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], sm, F[k], g, mg->h[k], nu2, st);
   }
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   return set_error(UPS_OK, "");

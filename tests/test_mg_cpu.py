@@ -28,7 +28,8 @@ def test_shapes_and_sizes():
     want = r256(8 * 9)
     want = r256(want + 20 * 18 * 22 * el)
     want = r256(want + 13 * 11 * 15 * el)
-    want = r256(want + 13 * 11 * 15 * el)              # one residual array, the largest refined level
+    want = r256(want + 13 * 11 * 15 * el)              # the residual, the largest refined level
+    want = r256(want + 13 * 11 * 15 * el)              # the smoother's second buffer, as large
     want = r256(want + 7 * 6 * 8 * el)
     want = r256(want + 5 * 4 * 6 * el)
     assert mg.work_bytes == want
@@ -330,3 +331,126 @@ def test_fused_smoothing_writes_every_node_once(n0, patches, prec):
                 np.add.at(hit, (q, Y[ok], X[ok]), 1)
                 np.add.at(hit, (q, fy[gh], fx[gh]), 1)
         assert (hit == 1).all(), (nz, ny, nx, np.argwhere(hit != 1)[:5])
+
+
+# tile shapes of the last pre-smoothing iteration fused with the residual
+GR32 = [(128, 16, 1024), (64, 16, 1024)]
+GR64 = [(128, 8, 1024), (64, 16, 1024)]
+
+
+def _gr_shape(prec, nx):
+    shapes = GR64 if prec == "f64" else GR32
+    padded = [(nx - 2 + tx) // tx * tx for tx, _, _ in shapes]
+    return shapes[padded.index(min(padded))]
+
+
+def _gr_frame(tx, ty, w=3):
+    """Frame columns (lx, ly, depth) of width 3 around a tx x ty tile in the
+    kernel's order: ring d (the border of the box of (ux - 2d) x (uy - 2d)
+    at (d, d)) from the outside in, each as top row, bottom row, then the two
+    side columns row by row."""
+    ux, uy = tx + 2 * w, ty + 2 * w
+    out = []
+    for r in range(ux * uy - tx * ty):
+        q, wd, hh, dep = r, ux, uy, 0
+        while dep < w - 1 and q >= 2 * wd + 2 * (hh - 2):
+            q -= 2 * wd + 2 * (hh - 2)
+            dep, wd, hh = dep + 1, wd - 2, hh - 2
+        if q < wd:
+            lx, ly = dep + q, dep
+        elif q < 2 * wd:
+            lx, ly = dep + q - wd, dep + hh - 1
+        else:
+            q2 = q - 2 * wd
+            lx, ly = dep + (wd - 1 if q2 & 1 else 0), dep + 1 + (q2 >> 1)
+        out.append((lx, ly, dep))
+    return out
+
+
+def test_fused_residual_shape_choice():
+    assert _gr_shape("f32", 513) == (128, 16, 1024)
+    assert _gr_shape("f32", 257) == (128, 16, 1024)
+    assert _gr_shape("f32", 301) == (64, 16, 1024)
+    assert _gr_shape("f64", 513) == (128, 8, 1024)
+    assert _gr_shape("f64", 41) == (64, 16, 1024)
+
+
+@pytest.mark.parametrize("shape", sorted(set(GR32 + GR64)))
+def test_fused_residual_frame_and_lds(shape):
+    tx, ty, nt = shape
+    ux, uy = tx + 6, ty + 6
+    assert tx * ty % nt == 0
+    frame = _gr_frame(tx, ty)
+    cols = [(lx, ly) for lx, ly, _ in frame]
+    assert len(set(cols)) == len(cols)
+    inner = {(3 + e % tx, 3 + e // tx) for e in range(tx * ty)}
+    assert inner.isdisjoint(cols) and len(inner) + len(cols) == ux * uy
+    # a frame column's depth is its distance to the frame's outer border
+    for lx, ly, d in frame:
+        assert d == min(lx, ly, ux - 1 - lx, uy - 1 - ly) and 0 <= d <= 2
+    depth = {(lx, ly): d for lx, ly, d in frame}
+    depth.update({c: 3 for c in inner})
+    red = [c for c, d in depth.items() if d >= 1]
+    black = [c for c, d in depth.items() if d >= 2]
+    assert len(red) == (tx + 4) * (ty + 4) and len(black) == (tx + 2) * (ty + 2)
+    for lx, ly in red:
+        # U (halo 3) at +-1; H written at (lx - 1, ly - 1)
+        assert 0 <= lx - 1 and lx + 1 < ux and 0 <= ly - 1 and ly + 1 < uy
+        assert 0 <= lx - 1 < tx + 4 and 0 <= ly - 1 < ty + 4
+    for lx, ly in black:
+        # H read at (lx - 1 +-1, ly - 1 +-1), a red column each; V written at (lx - 2, ly - 2)
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            assert depth[(lx + dx, ly + dy)] >= 1
+            assert 0 <= lx - 1 + dx < tx + 4 and 0 <= ly - 1 + dy < ty + 4
+        assert 0 <= lx - 2 < tx + 2 and 0 <= ly - 2 < ty + 2
+    for lx, ly in inner:
+        # the residual reads V at (lx - 2 +-1, ly - 2 +-1), a black column each
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            assert depth[(lx + dx, ly + dy)] >= 2
+            assert 0 <= lx - 2 + dx < tx + 2 and 0 <= ly - 2 + dy < ty + 2
+    # f is read from depth 1 in; the outer ring reads its inner neighbour's
+    for lx, ly, d in frame:
+        assert depth[(min(max(lx, 1), ux - 2), min(max(ly, 1), uy - 2))] >= 1
+    # register rings: u_in at p - 1 .. p + 2 (plane p + 3 loads into the slot
+    # of p - 1 after the red step), f at p - 2 .. p (plane p + 1 loads into the
+    # slot of p - 3 after the residual), H at p - 2 .. p, V at p - 3 .. p - 1
+    for k in range(4):
+        assert (k + 3) % 4 == (k - 1) % 4 and (k + 1) % 4 == (k - 3) % 4
+
+
+@pytest.mark.parametrize("n0,patches", HIERARCHIES + [((513, 70, 67), []), ((33, 65, 513), []),
+                                                        ((30, 24, 140), [((4, 4, 5), (20, 16, 128))])])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_residual_writes_every_node_once(n0, patches, prec):
+    # every node of the level gets u once and every unknown gets r once; the
+    # steps p0 = zs - 2 .. ze + 1 produce red at p, black at p - 1 and the
+    # residual at p - 2, so the chunk's planes zs .. ze - 1 are all reached
+    for nz, ny, nx in _levels(n0, patches):
+        tx, ty, nt = _gr_shape(prec, nx)
+        hit = np.zeros((nz, ny, nx), int)
+        rhit = np.zeros((nz, ny, nx), int)
+        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
+        ntiles = nty * ntx * ((nz - 2 + GS_ZC) // GS_ZC)
+        frame = np.array([(lx, ly) for lx, ly, _ in _gr_frame(tx, ty)])
+        for unit in range(ntiles):
+            tyi, txi, tzi = unit % nty, (unit // nty) % ntx, unit // (nty * ntx)
+            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * GS_ZC
+            ze = min(zs + GS_ZC, nz)
+            X, Y = np.meshgrid(x0 + np.arange(tx), y0 + np.arange(ty), indexing="xy")
+            ok = (X < nx) & (Y < ny)
+            fx, fy = x0 - 3 + frame[:, 0], y0 - 3 + frame[:, 1]
+            fin = (fx >= 0) & (fy >= 0) & (fx < nx) & (fy < ny)
+            gh = fin & (((fx == 0) & ((fy >= y0) | (fy == 0)) & (fy < y0 + ty)) | ((fy == 0) & (fx >= x0) & (fx < x0 + tx)))
+            p0, pe = zs - 2, ze + 1
+            steps = range(p0, pe + 1)
+            planes = [p - 1 for p in steps if zs <= p - 1 < ze] + ([0] if 0 in steps else [])
+            for q in planes:
+                np.add.at(hit, (q, Y[ok], X[ok]), 1)
+                np.add.at(hit, (q, fy[gh], fx[gh]), 1)
+            unk = ok & (X <= nx - 2) & (Y <= ny - 2)
+            for q in [p - 2 for p in steps if zs <= p - 2 < ze and 1 <= p - 2 <= nz - 2]:
+                np.add.at(rhit, (q, Y[unk], X[unk]), 1)
+        assert (hit == 1).all(), (nz, ny, nx, np.argwhere(hit != 1)[:5])
+        want = np.zeros((nz, ny, nx), int)
+        want[1:-1, 1:-1, 1:-1] = 1
+        assert np.array_equal(rhit, want)
