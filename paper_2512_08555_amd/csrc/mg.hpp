@@ -25,10 +25,10 @@ hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp
 // nu red-black iterations on u, the same values as 2 nu half-steps (red:
 // every unknown with (x + y + z) even set to (sum of its six neighbours -
 // h^2 f) / 6, then black): whole iterations by the fused kernel, u -> s ->
-// u ..., and a copy back into u after an odd count (s: a scratch array of
-// the level's size)
+// u ..., and a copy back into u if they end in s (s: a scratch array of the
+// level's size).  With from_s the values start in s instead of u.
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
-                                hipStream_t st);
+                                hipStream_t st, bool from_s = false);
 
 // nu red-black iterations on u as mg_smooth_iterations, then r = f - Lap u
 // on the unknowns, the last iteration and the residual in one kernel (s: a
@@ -45,10 +45,10 @@ hipError_t mg_residual(bool f64, const void* u, const void* f, void* r, MgGrid g
 hipError_t mg_restrict(bool f64, const void* u, const void* r, MgGrid g, void* up, void* fp, void* uhat, MgGrid gp,
                        MgBox b, double hp, hipStream_t st);
 
-// unknowns of u += trilinear prolongation of (up - uhat); ghost layer =
-// cubic reconstruction from up
-hipError_t mg_prolong(bool f64, void* u, MgGrid g, const void* up, const void* uhat, MgGrid gp, MgBox b,
-                      hipStream_t st);
+// unknowns of u = those of uin + trilinear prolongation of (up - uhat)
+// (uin may be u); ghost layer of u = cubic reconstruction from up
+hipError_t mg_prolong(bool f64, const void* uin, void* u, MgGrid g, const void* up, const void* uhat, MgGrid gp,
+                      MgBox b, hipStream_t st);
 
 // *out = max(*out, max |f - Lap u|) over the unknowns of g outside the
 // interior of the footprint of `child` (none if null); *out must start at 0

@@ -192,8 +192,12 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   if (s != UPS_OK) return s;
   for (int k = 1; k <= L && e == hipSuccess; ++k) {
     const MgGrid& g = mg->grid[k];
-    e = mg_prolong(f64, u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1], mg->box[k - 1], st);
-    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], sm, F[k], g, mg->h[k], nu2, st);
+    // after an odd nu2 the iterations end where they did not start: the
+    // prolongation then writes into the scratch array, and no copy is needed
+    const bool odd = nu2 & 1;
+    e = mg_prolong(f64, u[k], odd ? sm : u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1],
+                   mg->box[k - 1], st);
+    if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], sm, F[k], g, mg->h[k], nu2, st, odd);
   }
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   return set_error(UPS_OK, "");

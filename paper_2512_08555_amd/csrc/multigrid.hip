@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "mg.hpp"
 
@@ -608,8 +609,10 @@ __global__ void __launch_bounds__(kBX * kBY) k_mg_restrict(const T* __restrict__
 // index is m), from the correction at the corners of its coarse cell, so
 // neighbouring threads write neighbouring fine pairs and share their
 // corner loads.  Fine nodes on the ghost layer are left to the ghost kernel.
+// It reads u_in and writes u_out = u_in + correction at every fine unknown:
+// the two may be one array (each node is read and written by one thread).
 template <typename T>
-__global__ void __launch_bounds__(kBX * kBY) k_mg_prolong(T* __restrict__ u, MgGrid g, const T* __restrict__ up,
+__global__ void __launch_bounds__(kBX * kBY) k_mg_prolong(const T* uin, T* uout, MgGrid g, const T* __restrict__ up,
                                                           const T* __restrict__ uhat, MgGrid gp, MgBox b) {
   const int k = blockIdx.z;
   const int j = blockIdx.y * kBY + threadIdx.y;
@@ -644,8 +647,8 @@ __global__ void __launch_bounds__(kBX * kBY) k_mg_prolong(T* __restrict__ u, MgG
         yv[di] = bb ? T(0.5) * (z0 + z1) : z0;
       }
       const size_t row = ((size_t)z * g.ny + y) * g.nx;
-      if (i > 0 && i < b.mx) u[row + 2 * i] += yv[0];
-      if (i < b.mx) u[row + 2 * i + 1] += T(0.5) * (yv[0] + yv[1]);
+      if (i > 0 && i < b.mx) uout[row + 2 * i] = uin[row + 2 * i] + yv[0];
+      if (i < b.mx) uout[row + 2 * i + 1] = uin[row + 2 * i + 1] + T(0.5) * (yv[0] + yv[1]);
     }
   }
 }
@@ -779,14 +782,18 @@ hipError_t smooth_fused(bool f64, const void* a, void* b, const void* f, MgGrid 
 }  // namespace
 
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
-                                hipStream_t st) {
-  // nu fused iterations, alternately u -> s and s -> u; after an odd count
-  // the result is in s and is copied back (2 arrays of traffic, against the 3
-  // of an iteration split into two in-place half-steps)
+                                hipStream_t st, bool from_s) {
+  // nu fused iterations, alternately between u and s from wherever the
+  // values are; if they end in s they are copied back (2 arrays of traffic,
+  // against the 3 of an iteration split into two in-place half-steps)
   hipError_t e = hipSuccess;
-  for (int it = 0; it < nu && e == hipSuccess; ++it)
-    e = (it & 1) ? smooth_fused(f64, s, u, f, g, h, st) : smooth_fused(f64, u, s, f, g, h, st);
-  if (e == hipSuccess && (nu & 1))
+  void* a = from_s ? s : u;
+  void* b = from_s ? u : s;
+  for (int it = 0; it < nu && e == hipSuccess; ++it) {
+    e = smooth_fused(f64, a, b, f, g, h, st);
+    std::swap(a, b);
+  }
+  if (e == hipSuccess && a == s)
     e = hipMemcpyAsync(u, s, (size_t)g.nx * g.ny * g.nz * (f64 ? sizeof(double) : sizeof(float)),
                        hipMemcpyDeviceToDevice, st);
   return e;
@@ -834,14 +841,14 @@ hipError_t mg_restrict(bool f64, const void* u, const void* r, MgGrid g, void* u
   return hipGetLastError();
 }
 
-hipError_t mg_prolong(bool f64, void* u, MgGrid g, const void* up, const void* uhat, MgGrid gp, MgBox b,
-                      hipStream_t st) {
+hipError_t mg_prolong(bool f64, const void* uin, void* u, MgGrid g, const void* up, const void* uhat, MgGrid gp,
+                      MgBox b, hipStream_t st) {
   const dim3 grid = grid_xyz(b.mx + 1, b.my + 1, b.mz + 1), block(kBX, kBY);
   if (f64)
-    hipLaunchKernelGGL(k_mg_prolong<double>, grid, block, 0, st, static_cast<double*>(u), g,
+    hipLaunchKernelGGL(k_mg_prolong<double>, grid, block, 0, st, static_cast<const double*>(uin), static_cast<double*>(u), g,
                        static_cast<const double*>(up), static_cast<const double*>(uhat), gp, b);
   else
-    hipLaunchKernelGGL(k_mg_prolong<float>, grid, block, 0, st, static_cast<float*>(u), g,
+    hipLaunchKernelGGL(k_mg_prolong<float>, grid, block, 0, st, static_cast<const float*>(uin), static_cast<float*>(u), g,
                        static_cast<const float*>(up), static_cast<const float*>(uhat), gp, b);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? mg_fill_ghosts(f64, u, g, up, gp, b, st) : e;

@@ -147,7 +147,9 @@ def test_transfer_kernels_stay_in_bounds(n0, patches):
         mz, my, mx = m
         # prolongation: one thread per footprint node (i, j, k) writes the fine
         # unknowns 2 (i, j, k) + (a, b, c) (a = 0 only where i = m), never a
-        # ghost node, each unknown exactly once; it reads the cell corners
+        # ghost node, each unknown exactly once; it reads the cell corners.
+        # With the ghost kernel it writes every node of the level, which is
+        # what lets the cycle prolong into the smoother's scratch array
         bx, by, bz, tx, ty = _threads(_grid(mx + 1, my + 1, mz + 1), (BX, BY))
         k, j, i = bz, by * BY + ty, bx * BX + tx
         ok = (j <= my) & (i <= mx)
