@@ -443,9 +443,10 @@ ups_status ups_mg_create(ups_plan_t coarse, const ups_mg_hierarchy* hier, ups_mg
 /* Node counts (x, y, z) of level 0 .. l. */
 ups_status ups_mg_level_shape(ups_mg_t mg, int level, int n[3]);
 
-/* Bytes of the work buffer: the modified sources of levels 0 .. l-1, two
- * arrays of the largest refined level (the smoother's second buffer and the
- * residual), the stored footprints and the residual norms. */
+/* Bytes of the work buffer: the modified sources of levels 0 .. l-1, the
+ * smoother's second array of each refined level, one array of the largest
+ * refined level (the residual), the stored footprints and the residual
+ * norms. */
 ups_status ups_mg_sizes(ups_mg_t mg, size_t* work_bytes);
 
 /* Bind the caller's work buffer (256-byte aligned, at least ups_mg_sizes

@@ -30,11 +30,13 @@ hipError_t mg_fill_ghosts(bool f64, void* u, MgGrid g, const void* up, MgGrid gp
 hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGrid g, double h, int nu,
                                 hipStream_t st, bool from_s = false);
 
-// nu red-black iterations on u as mg_smooth_iterations, then r = f - Lap u
-// on the unknowns, the last iteration and the residual in one kernel (s: a
-// scratch array of the level's size, different from r)
+// nu red-black iterations from u, alternately into s and back, then r =
+// f - Lap u on the unknowns, the last iteration and the residual in one
+// kernel.  The smoothed values end in u after an even nu and in s after an
+// odd one; *out says which (s: a scratch array of the level's size,
+// different from r)
 hipError_t mg_smooth_residual(bool f64, void* u, void* s, const void* f, void* r, MgGrid g, double h, int nu,
-                              hipStream_t st);
+                              hipStream_t st, void** out);
 
 // r = f - Lap u on the unknowns (the ghost layer of r is not written)
 hipError_t mg_residual(bool f64, const void* u, const void* f, void* r, MgGrid g, double h, hipStream_t st);

@@ -24,7 +24,8 @@ struct ups_mg_s {
   std::vector<double> h;          // spacing of each level
   std::vector<size_t> off_F;      // modified sources of levels 0 .. l-1
   std::vector<size_t> off_uhat;   // stored footprint of box k+1 at index k
-  size_t off_norm = 0, off_r = 0, off_s = 0, bytes = 0;
+  std::vector<size_t> off_s;     // the smoother's scratch array of level k at index k - 1
+  size_t off_norm = 0, off_r = 0, bytes = 0;
   void* work = nullptr;
 };
 
@@ -111,8 +112,10 @@ ups_status ups_mg_create(ups_plan_t coarse, const ups_mg_hierarchy* hier, ups_mg
   for (int k = 1; k <= mg->levels; ++k) rmax = std::max(rmax, nodes(mg->grid[k]) * el);
   mg->off_r = off;
   off = align256(off + rmax);
-  mg->off_s = off;
-  off = align256(off + rmax);
+  for (int k = 1; k <= mg->levels; ++k) {
+    mg->off_s.push_back(off);
+    off = align256(off + nodes(mg->grid[k]) * el);
+  }
   for (int k = 0; k < mg->levels; ++k) {
     const MgBox& b = mg->box[k];
     mg->off_uhat.push_back(off);
@@ -173,7 +176,10 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   for (int k = 0; k < L; ++k) F[k] = wb + mg->off_F[k];
   F[L] = const_cast<void*>(f[L]);
   void* r = wb + mg->off_r;
-  void* sm = wb + mg->off_s;
+  // where each refined level's pre-smoothed values are: u[k] or its scratch
+  // array, which no other level touches, so they stay there until the
+  // prolongation reads them
+  std::vector<void*> cur(L + 1);
   hipError_t e = hipSuccess;
   for (int k = 0; k < L && e == hipSuccess; ++k)
     e = hipMemcpyAsync(F[k], f[k], nodes(mg->grid[k]) * el, hipMemcpyDeviceToDevice, st);
@@ -182,9 +188,10 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
     const MgGrid& gp = mg->grid[k - 1];
     const MgBox& b = mg->box[k - 1];
     e = mg_fill_ghosts(f64, u[k], g, u[k - 1], gp, b, st);
-    if (e == hipSuccess) e = mg_smooth_residual(f64, u[k], sm, F[k], r, g, mg->h[k], nu1, st);
     if (e == hipSuccess)
-      e = mg_restrict(f64, u[k], r, g, u[k - 1], F[k - 1], wb + mg->off_uhat[k - 1], gp, b, mg->h[k - 1], st);
+      e = mg_smooth_residual(f64, u[k], wb + mg->off_s[k - 1], F[k], r, g, mg->h[k], nu1, st, &cur[k]);
+    if (e == hipSuccess)
+      e = mg_restrict(f64, cur[k], r, g, u[k - 1], F[k - 1], wb + mg->off_uhat[k - 1], gp, b, mg->h[k - 1], st);
   }
   if (e != hipSuccess) return set_error(UPS_ERR_DEVICE, hipGetErrorString(e));
   ups_plan_t p = mg->plan;
@@ -192,10 +199,11 @@ ups_status ups_mg_cycle(ups_mg_t mg, const void* const* f, void* const* u, int n
   if (s != UPS_OK) return s;
   for (int k = 1; k <= L && e == hipSuccess; ++k) {
     const MgGrid& g = mg->grid[k];
+    void* sm = wb + mg->off_s[k - 1];
     // after an odd nu2 the iterations end where they did not start: the
     // prolongation then writes into the scratch array, and no copy is needed
     const bool odd = nu2 & 1;
-    e = mg_prolong(f64, u[k], odd ? sm : u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1],
+    e = mg_prolong(f64, cur[k], odd ? sm : u[k], g, u[k - 1], wb + mg->off_uhat[k - 1], mg->grid[k - 1],
                    mg->box[k - 1], st);
     if (e == hipSuccess) e = mg_smooth_iterations(f64, u[k], sm, F[k], g, mg->h[k], nu2, st, odd);
   }

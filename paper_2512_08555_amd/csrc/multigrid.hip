@@ -800,19 +800,20 @@ hipError_t mg_smooth_iterations(bool f64, void* u, void* s, const void* f, MgGri
 }
 
 hipError_t mg_smooth_residual(bool f64, void* u, void* s, const void* f, void* r, MgGrid g, double h, int nu,
-                              hipStream_t st) {
+                              hipStream_t st, void** out) {
+  *out = u;
   if (nu == 0) return mg_residual(f64, u, f, r, g, h, st);
   // nu - 1 plain iterations, u -> s -> u ..., then the fused one from
-  // wherever they left the values; it writes u itself after an even count
+  // wherever they left the values; they end in s after an odd count
   hipError_t e = hipSuccess;
-  for (int it = 0; it + 1 < nu && e == hipSuccess; ++it)
-    e = (it & 1) ? smooth_fused(f64, s, u, f, g, h, st) : smooth_fused(f64, u, s, f, g, h, st);
-  if (e != hipSuccess) return e;
-  const bool from_s = (nu - 1) & 1;
-  e = from_s ? smooth_residual_fused(f64, s, u, f, r, g, h, st) : smooth_residual_fused(f64, u, s, f, r, g, h, st);
-  if (e == hipSuccess && !from_s)
-    e = hipMemcpyAsync(u, s, (size_t)g.nx * g.ny * g.nz * (f64 ? sizeof(double) : sizeof(float)),
-                       hipMemcpyDeviceToDevice, st);
+  void* a = u;
+  void* b = s;
+  for (int it = 0; it + 1 < nu && e == hipSuccess; ++it) {
+    e = smooth_fused(f64, a, b, f, g, h, st);
+    std::swap(a, b);
+  }
+  if (e == hipSuccess) e = smooth_residual_fused(f64, a, b, f, r, g, h, st);
+  *out = b;
   return e;
 }
 

@@ -29,7 +29,8 @@ def test_shapes_and_sizes():
     want = r256(want + 20 * 18 * 22 * el)
     want = r256(want + 13 * 11 * 15 * el)
     want = r256(want + 13 * 11 * 15 * el)              # the residual, the largest refined level
-    want = r256(want + 13 * 11 * 15 * el)              # the smoother's second buffer, as large
+    want = r256(want + 13 * 11 * 15 * el)              # the smoother's second array of level 1
+    want = r256(want + 9 * 7 * 11 * el)                # and of level 2
     want = r256(want + 7 * 6 * 8 * el)
     want = r256(want + 5 * 4 * 6 * el)
     assert mg.work_bytes == want
