@@ -2,10 +2,12 @@
 // Gauss-Seidel, residual, full-weighting restriction with injection and the
 // full-approximation right-hand side, trilinear prolongation of the
 // correction, cubic reconstruction of the ghost layers and residual norms.
-// All are bound by HBM traffic: one thread per node, 64 threads along x,
-// neighbours of a node come from the caches.  The
-// arithmetic follows the order of the definitions (interpolation and full
-// weighting one axis at a time, z, then y, then x).
+// All are bound by HBM traffic.  The smoother (k_mg_gs2, and k_mg_gsr, its
+// last pre-smoothing iteration fused with the residual) marches tiles up
+// chunks of planes with LDS and register rings; the others take one thread
+// per node, 64 threads along x, and the neighbours of a node from the
+// caches.  The arithmetic follows the order of the definitions
+// (interpolation and full weighting one axis at a time, z, then y, then x).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
