@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(256) k_mg_ghosts(T* __restrict__ u, MgGrid g, 
 // the same arithmetic as a red half-step followed by a black one.
 //
 // Tiles start at node 1: a block owns TX x TY columns (x0 .. x0 + TX - 1,
-// y0 .. y0 + TY - 1, x0 and y0 = 1 mod TX and TY) and a chunk of kZC
-// planes from zs = 1 mod kZC, and marches up z.  Levels of 2^k + 1 nodes
+// y0 .. y0 + TY - 1, x0 and y0 = 1 mod TX and TY) and a chunk of zc
+// planes from zs = 1 mod zc, and marches up z.  Levels of 2^k + 1 nodes
 // then split into whole tiles; the ghost nodes at index 0 belong to no tile
 // and are written through by the blocks next to them.
 //
@@ -147,7 +147,6 @@ __global__ void __launch_bounds__(256) k_mg_ghosts(T* __restrict__ u, MgGrid g, 
 // wave-uniform plane base plus a 32-bit byte offset in the plane: the cycle
 // smooths refined levels only, which hold at most 2^31 - 1 nodes in at least
 // 5 planes, so a plane stays below 2^32 bytes in FP64.
-constexpr int kZC = 32;
 
 template <int K>
 struct Slot {
@@ -156,7 +155,7 @@ struct Slot {
 
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_mg_gs2(const T* __restrict__ uin, T* __restrict__ uout,
-                                               const T* __restrict__ f, MgGrid g, T h2) {
+                                               const T* __restrict__ f, MgGrid g, T h2, int zc) {
   constexpr int UX = TX + 4, UY = TY + 4, HX = TX + 2, HY = TY + 2;
   static_assert((TX * TY) % NT == 0, "interior columns split evenly over the threads");
   constexpr int NI = TX * TY / NT;          // interior columns per thread
@@ -168,13 +167,13 @@ __global__ void __launch_bounds__(NT) k_mg_gs2(const T* __restrict__ uin, T* __r
   // contiguous run of tiles ordered y fastest, then x, then z chunk, so that
   // tiles sharing halo rows run on the same XCD (its L2) at about the same time
   const int nty = (g.ny - 1 + TY - 1) / TY, ntx = (g.nx - 1 + TX - 1) / TX;
-  const int ntiles = nty * ntx * ((g.nz - 1 + kZC - 1) / kZC);
+  const int ntiles = nty * ntx * ((g.nz - 1 + zc - 1) / zc);
   const int per_xcd = (ntiles + 7) / 8;
   const int unit = int(blockIdx.x % 8) * per_xcd + int(blockIdx.x / 8);
   if (unit >= ntiles) return;
   const int tyi = unit % nty, txi = (unit / nty) % ntx, tzi = unit / (nty * ntx);
   const int x0 = 1 + txi * TX, y0 = 1 + tyi * TY;
-  const int zs = 1 + tzi * kZC, ze = min(zs + kZC, g.nz);
+  const int zs = 1 + tzi * zc, ze = min(zs + zc, g.nz);
   const int t = threadIdx.x;
   const size_t sz = (size_t)g.nx * g.ny;
   auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
@@ -371,7 +370,7 @@ __global__ void __launch_bounds__(NT) k_mg_gs2(const T* __restrict__ uin, T* __r
 // those of k_mg_gs2; the three LDS planes are double-buffered by parity.
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_mg_gsr(const T* __restrict__ uin, T* __restrict__ uout,
-                                               const T* __restrict__ f, T* __restrict__ r, MgGrid g, T h2) {
+                                               const T* __restrict__ f, T* __restrict__ r, MgGrid g, T h2, int zc) {
   constexpr int W = 3, UX = TX + 2 * W, UY = TY + 2 * W;
   static_assert((TX * TY) % NT == 0, "interior columns split evenly over the threads");
   constexpr int NI = TX * TY / NT;
@@ -381,13 +380,13 @@ __global__ void __launch_bounds__(NT) k_mg_gsr(const T* __restrict__ uin, T* __r
   __shared__ T Hs[2][TY + 4][TX + 4];
   __shared__ T Vs[2][TY + 2][TX + 2];
   const int nty = (g.ny - 1 + TY - 1) / TY, ntx = (g.nx - 1 + TX - 1) / TX;
-  const int ntiles = nty * ntx * ((g.nz - 1 + kZC - 1) / kZC);
+  const int ntiles = nty * ntx * ((g.nz - 1 + zc - 1) / zc);
   const int per_xcd = (ntiles + 7) / 8;
   const int unit = int(blockIdx.x % 8) * per_xcd + int(blockIdx.x / 8);
   if (unit >= ntiles) return;
   const int tyi = unit % nty, txi = (unit / nty) % ntx, tzi = unit / (nty * ntx);
   const int x0 = 1 + txi * TX, y0 = 1 + tyi * TY;
-  const int zs = 1 + tzi * kZC, ze = min(zs + kZC, g.nz);
+  const int zs = 1 + tzi * zc, ze = min(zs + zc, g.nz);
   const int t = threadIdx.x;
   const size_t sz = (size_t)g.nx * g.ny;
   auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
@@ -733,12 +732,58 @@ int gs_shape(const GsShape* c, int n, int nx) {
   return best;
 }
 
+// Planes per z chunk of the tiled smoothers.  A block pays the start of its
+// plane pipeline (four planes of loads before the first store) once per
+// chunk, so long chunks are cheaper, as long as the tiles still fill the
+// GPU.  The chunk count n minimises rounds(n) (ceil(planes / n) + 8), where
+// rounds(n) is how many times the n * layer blocks (layer = tiles per plane)
+// refill `slots` resident blocks.  Measured at 513^3 (FP32 256 x 8 tiles, one
+// block per CU, 128 tiles per plane): 2 chunks of 256 planes 375 us, 4 of 128
+// 387 us, 16 of 32 431-468 us; at 257^3 (32 tiles per plane), 8 chunks of 32
+// planes 47 us, 2 of 128 148 us.
+int chunk_planes(long long layer, int planes, long long slots) {
+  int best_n = 1;
+  long long best = -1;
+  const int nmax = std::max(1, planes / 8);
+  for (int n = 1; n <= nmax; ++n) {
+    const long long zc = (planes + n - 1) / n;
+    const long long rounds = (layer * n + slots - 1) / slots;
+    const long long cost = rounds * (zc + 8);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_n = n;
+    }
+  }
+  return (planes + best_n - 1) / best_n;
+}
+
+// Blocks of `kernel` (nt threads) one compute unit holds, at least 1.
+int blocks_per_cu(const void* kernel, int nt) {
+  int n = 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, nt, 0) == hipSuccess ? std::max(n, 1) : 1;
+}
+
+// Chunk length and grid of a tiled smoother over level g: the blocks the
+// current device holds at once are its compute units times per_cu.
+void tile_grid(int tx, int ty, MgGrid g, int per_cu, int* zc, unsigned* blocks) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 1;
+  const long long layer = (long long)((g.nx - 1 + tx - 1) / tx) * ((g.ny - 1 + ty - 1) / ty);
+  *zc = chunk_planes(layer, g.nz - 1, (long long)std::max(cus, 1) * per_cu);
+  const long long ntiles = layer * ((g.nz - 1 + *zc - 1) / *zc);
+  *blocks = unsigned(8 * ((ntiles + 7) / 8));
+}
+
 template <typename T, int TX, int TY, int NT>
 hipError_t launch_gs2(const void* a, void* b, const void* f, MgGrid g, double h, hipStream_t st) {
-  const long long ntiles =
-      (long long)((g.nx - 1 + TX - 1) / TX) * ((g.ny - 1 + TY - 1) / TY) * ((g.nz - 1 + kZC - 1) / kZC);
-  hipLaunchKernelGGL((k_mg_gs2<T, TX, TY, NT>), dim3(unsigned(8 * ((ntiles + 7) / 8))), dim3(NT), 0, st,
-                     static_cast<const T*>(a), static_cast<T*>(b), static_cast<const T*>(f), g, T(h * h));
+  static const int per_cu = blocks_per_cu(reinterpret_cast<const void*>(k_mg_gs2<T, TX, TY, NT>), NT);
+  int zc = 0;
+  unsigned blocks = 0;
+  tile_grid(TX, TY, g, per_cu, &zc, &blocks);
+  hipLaunchKernelGGL((k_mg_gs2<T, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, static_cast<const T*>(a),
+                     static_cast<T*>(b), static_cast<const T*>(f), g, T(h * h), zc);
   return hipGetLastError();
 }
 
@@ -749,11 +794,12 @@ constexpr GsShape kGr64[] = {{128, 8, 1024}, {64, 16, 1024}};
 
 template <typename T, int TX, int TY, int NT>
 hipError_t launch_gsr(const void* a, void* b, const void* f, void* r, MgGrid g, double h, hipStream_t st) {
-  const long long ntiles =
-      (long long)((g.nx - 1 + TX - 1) / TX) * ((g.ny - 1 + TY - 1) / TY) * ((g.nz - 1 + kZC - 1) / kZC);
-  hipLaunchKernelGGL((k_mg_gsr<T, TX, TY, NT>), dim3(unsigned(8 * ((ntiles + 7) / 8))), dim3(NT), 0, st,
-                     static_cast<const T*>(a), static_cast<T*>(b), static_cast<const T*>(f), static_cast<T*>(r), g,
-                     T(h * h));
+  static const int per_cu = blocks_per_cu(reinterpret_cast<const void*>(k_mg_gsr<T, TX, TY, NT>), NT);
+  int zc = 0;
+  unsigned blocks = 0;
+  tile_grid(TX, TY, g, per_cu, &zc, &blocks);
+  hipLaunchKernelGGL((k_mg_gsr<T, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, static_cast<const T*>(a),
+                     static_cast<T*>(b), static_cast<const T*>(f), static_cast<T*>(r), g, T(h * h), zc);
   return hipGetLastError();
 }
 

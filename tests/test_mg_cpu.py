@@ -230,7 +230,38 @@ def test_residual_norm_rows_cover_the_unknowns_once(n0, patches):
 # tile shapes of the fused red-black iteration (x width, y height, threads)
 GS32 = [(256, 8, 1024), (128, 16, 1024), (64, 16, 512)]
 GS64 = [(128, 16, 1024), (64, 16, 512)]
-GS_ZC = 32
+
+
+def _chunk_planes(layer, planes, slots):
+    """Planes per z chunk: the chunk count n minimises rounds(n) (ceil(planes
+    / n) + 8), rounds(n) = ceil(n layer / slots), over n <= planes / 8, the
+    first minimum kept."""
+    best = None
+    for n in range(1, max(1, planes // 8) + 1):
+        zc = -(-planes // n)
+        cost = -(-(layer * n) // slots) * (zc + 8)
+        if best is None or cost < best[0]:
+            best = (cost, zc)
+    return best[1]
+
+
+def _chunks(layer, nz):
+    # the rule's choice with one and with two resident blocks per CU on 256
+    # CUs, and two fixed lengths (coverage holds for any chunk length)
+    return sorted({_chunk_planes(layer, nz - 1, 256), _chunk_planes(layer, nz - 1, 512), 7, 32})
+
+
+def test_chunk_rule():
+    # 513^3: 128 tiles per plane, one block per CU -> 2 chunks of 256 planes;
+    # 257^3: 32 tiles per plane -> 8 chunks of 32
+    assert _chunk_planes(128, 512, 256) == 256
+    assert _chunk_planes(32, 256, 256) == 32
+    assert _chunk_planes(2048, 512, 256) == 512      # many tiles per plane: one chunk
+    assert _chunk_planes(1, 4, 256) == 4              # fewer than 8 planes: one chunk
+    for layer in (1, 3, 32, 96, 128, 500):
+        for planes in (4, 40, 256, 512, 1000):
+            zc = _chunk_planes(layer, planes, 256)
+            assert 1 <= zc <= planes and (zc >= 8 or zc == planes)
 
 
 def _gs_shape(prec, nx):
@@ -301,15 +332,20 @@ def test_fused_smoothing_frame_and_lds(shape):
                                                         ((30, 24, 140), [((4, 4, 5), (20, 16, 128))])])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_smoothing_writes_every_node_once(n0, patches, prec):
-    # tiles from node 1 by chunks of 32 planes from plane 1 (the XCD-aware
+    # tiles from node 1 by chunks of zc planes from plane 1 (the XCD-aware
     # block order), the ghost faces at index 0 through the frame and the
     # first chunk: every node of the level is written exactly once, and the
     # loads (clamped) and stores stay in the level
+    cases = []
     for nz, ny, nx in _levels(n0, patches):
+        tx, ty, nt = _gs_shape(prec, nx)
+        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
+        cases += [(nz, ny, nx, zc) for zc in _chunks(nty * ntx, nz)]
+    for nz, ny, nx, zc in cases:
         tx, ty, nt = _gs_shape(prec, nx)
         hit = np.zeros((nz, ny, nx), int)
         nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
-        ntiles = nty * ntx * ((nz - 2 + GS_ZC) // GS_ZC)
+        ntiles = nty * ntx * ((nz - 2 + zc) // zc)
         per_xcd = (ntiles + 7) // 8
         frame = np.array(_gs_frame(tx, ty))
         units = []
@@ -320,8 +356,8 @@ def test_fused_smoothing_writes_every_node_once(n0, patches, prec):
         assert sorted(units) == list(range(ntiles))
         for unit in units:
             tyi, txi, tzi = unit % nty, (unit // nty) % ntx, unit // (nty * ntx)
-            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * GS_ZC
-            ze = min(zs + GS_ZC, nz)
+            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * zc
+            ze = min(zs + zc, nz)
             x = x0 + np.arange(tx)
             y = y0 + np.arange(ty)
             X, Y = np.meshgrid(x, y, indexing="xy")
@@ -428,17 +464,22 @@ def test_fused_residual_writes_every_node_once(n0, patches, prec):
     # every node of the level gets u once and every unknown gets r once; the
     # steps p0 = zs - 2 .. ze + 1 produce red at p, black at p - 1 and the
     # residual at p - 2, so the chunk's planes zs .. ze - 1 are all reached
+    cases = []
     for nz, ny, nx in _levels(n0, patches):
         tx, ty, nt = _gr_shape(prec, nx)
+        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
+        cases += [(nz, ny, nx, zc) for zc in _chunks(nty * ntx, nz)]
+    for nz, ny, nx, zc in cases:
+        tx, ty, nt = _gr_shape(prec, nx)
+        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
         hit = np.zeros((nz, ny, nx), int)
         rhit = np.zeros((nz, ny, nx), int)
-        nty, ntx = (ny - 2 + ty) // ty, (nx - 2 + tx) // tx
-        ntiles = nty * ntx * ((nz - 2 + GS_ZC) // GS_ZC)
+        ntiles = nty * ntx * ((nz - 2 + zc) // zc)
         frame = np.array([(lx, ly) for lx, ly, _ in _gr_frame(tx, ty)])
         for unit in range(ntiles):
             tyi, txi, tzi = unit % nty, (unit // nty) % ntx, unit // (nty * ntx)
-            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * GS_ZC
-            ze = min(zs + GS_ZC, nz)
+            x0, y0, zs = 1 + txi * tx, 1 + tyi * ty, 1 + tzi * zc
+            ze = min(zs + zc, nz)
             X, Y = np.meshgrid(x0 + np.arange(tx), y0 + np.arange(ty), indexing="xy")
             ok = (X < nx) & (Y < ny)
             fx, fy = x0 - 3 + frame[:, 0], y0 - 3 + frame[:, 1]
