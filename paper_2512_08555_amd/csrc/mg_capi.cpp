@@ -24,7 +24,7 @@ struct ups_mg_s {
   std::vector<double> h;          // spacing of each level
   std::vector<size_t> off_F;      // modified sources of levels 0 .. l-1
   std::vector<size_t> off_uhat;   // stored footprint of box k+1 at index k
-  std::vector<size_t> off_s;     // the smoother's scratch array of level k at index k - 1
+  std::vector<size_t> off_s;      // the smoother's scratch array of level k at index k - 1
   size_t off_norm = 0, off_r = 0, bytes = 0;
   void* work = nullptr;
 };
